@@ -1,0 +1,342 @@
+"""Pins for the FP64 oracle: each check compares it with something other than
+itself -- a library routine, a closed form, an exact rational identity, or
+brute force -- so that a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import oracle
+from oracle import schemes
+from paper_2101_02286_amd import synth
+
+
+def dense_matrix(bands, n, cyclic, per_row=False):
+    bands = np.asarray(bands, dtype=np.float64)
+    r = (bands.shape[-1] - 1) // 2
+    A = np.zeros((n, n))
+    for j in range(n):
+        row = bands[j] if per_row else bands
+        for o in range(-r, r + 1):
+            c = j + o
+            if cyclic:
+                A[j, c % n] += row[o + r]
+            elif 0 <= c < n:
+                A[j, c] = row[o + r]
+    return A
+
+
+# ---------------------------------------------------------------- solve ----
+@pytest.mark.parametrize("r", [1, 2, 3])
+@pytest.mark.parametrize("cyclic", [True, False])
+@pytest.mark.parametrize("n", [7, 8, 11, 16, 24, 33])
+def test_solve_vs_dense_lu(r, cyclic, n):
+    """Brute force on tiny n: numpy's dense LU on the assembled matrix."""
+    if cyclic and n < 2 * r + 1:
+        pytest.skip("cyclic needs n >= 2r+1")
+    bands = synth.random_bands(n, r, seed=n * 10 + r)
+    if not cyclic:  # entries outside the matrix must be zero
+        for j in range(n):
+            for o in range(-r, r + 1):
+                if not 0 <= j + o < n:
+                    bands[j, o + r] = 0.0
+    rng = np.random.default_rng(n + 100 * r)
+    b = rng.standard_normal((5, n))
+    x = oracle.solve_lines(b, bands, cyclic=cyclic, per_row=True)
+    A = dense_matrix(bands, n, cyclic, per_row=True)
+    xref = np.linalg.solve(A, b.T).T
+    assert np.abs(x - xref).max() <= 1e-13 * np.abs(xref).max()
+
+
+@pytest.mark.parametrize("scheme", ["deriv6", "deriv10", "interp6", "stag6"])
+@pytest.mark.parametrize("n", [32, 256, 512, 1000])
+def test_solve_vs_fft_circulant(scheme, n):
+    """Constant-coefficient cyclic A is circulant: diagonalised by the FFT,
+    eigenvalue lambda_k = sum_o a_o exp(i 2 pi k o / n)."""
+    s = dict(deriv6=schemes.DERIV6, deriv10=schemes.DERIV10, interp6=schemes.INTERP6,
+             stag6=schemes.STAG6)[scheme]
+    bands = np.array(schemes.bands_collocated(s) if "beta" in s else
+                     [float(s["alpha"]), 1.0, float(s["alpha"])])
+    r = (bands.size - 1) // 2
+    rng = np.random.default_rng(n)
+    b = rng.standard_normal((4, n))
+    x = oracle.solve_lines(b, bands)
+    theta = 2 * np.pi * np.arange(n) / n
+    lam = sum(bands[o + r] * np.exp(1j * theta * o) for o in range(-r, r + 1))
+    xref = np.fft.ifft(np.fft.fft(b, axis=1) / lam, axis=1).real
+    assert np.abs(x - xref).max() <= 5e-15 * math.sqrt(n) * np.abs(xref).max()
+
+
+def test_solve_acyclic_vs_scipy_banded():
+    """Acyclic banded: scipy's LAPACK banded solver (gbsv)."""
+    n, r = 300, 2
+    bands = synth.random_bands(n, r, seed=7)
+    for j in range(n):
+        for o in range(-r, r + 1):
+            if not 0 <= j + o < n:
+                bands[j, o + r] = 0.0
+    ab = np.zeros((2 * r + 1, n))  # LAPACK upper-first band layout
+    for j in range(n):
+        for o in range(-r, r + 1):
+            if 0 <= j + o < n:
+                ab[r - o, j + o] = bands[j, o + r]
+    b = np.random.default_rng(1).standard_normal(n)
+    xref = scipy.linalg.solve_banded((r, r), ab, b)
+    x = oracle.solve_lines(b, bands, cyclic=False, per_row=True)[0]
+    assert np.abs(x - xref).max() <= 1e-13 * np.abs(xref).max()
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_solve_residual_large(r):
+    """Backward error of a long per-row system: ||Ax-b|| <= c eps ||A|| ||x||."""
+    n = 4096
+    bands = synth.random_bands(n, r, seed=3)
+    b = np.random.default_rng(4).standard_normal((2, n))
+    x = oracle.solve_lines(b, bands, per_row=True)
+    Ax = np.zeros_like(x)
+    for o in range(-r, r + 1):
+        Ax += bands[:, o + r][None, :] * np.roll(x, -o, axis=1)
+    anorm = np.abs(bands).sum(axis=1).max()
+    assert np.abs(Ax - b).max() <= 20 * np.finfo(float).eps * anorm * np.abs(x).max()
+
+
+def test_singular_detected():
+    """[1/2, 1, 1/2] cyclic: eigenvalue 1 + cos(2 pi k/n) vanishes at k = n/2
+    when n is even; odd n is regular."""
+    b = np.ones((1, 16))
+    with pytest.raises(oracle.OracleError):
+        oracle.solve_lines(b, [0.5, 1.0, 0.5])
+    x = oracle.solve_lines(np.ones((1, 15)), [0.5, 1.0, 0.5])
+    assert np.allclose(x, 0.5)  # constant RHS: x = b / (1 + 2 * 0.5)
+
+
+# --------------------------------------------------------------- stencil ---
+@pytest.mark.parametrize("lo,coefs", [(-2, [0.1, -0.7, 0.0, 0.7, -0.1]), (-1, [0.05, 0.75, 0.75, 0.05]),
+                                      (-3, [1., 2., 3., 4., 5., 6., 7.])])
+def test_stencil_vs_dense_circulant(lo, coefs):
+    nz, ny, nx = 6, 7, 9
+    f = np.random.default_rng(5).standard_normal((nz, ny, nx))
+    for axis in range(3):
+        out = oracle.stencil_axis(f, axis, lo, coefs)
+        n = f.shape[2 - axis]
+        B = np.zeros((n, n))
+        for j in range(n):
+            for q, c in enumerate(coefs):
+                B[j, (j + lo + q) % n] += c
+        ref = np.moveaxis(np.tensordot(B, np.moveaxis(f, 2 - axis, 0), axes=(1, 0)), 0, 2 - axis)
+        assert np.abs(out - ref).max() <= 1e-13
+
+
+def test_axes_consistent_with_lines():
+    """solve_axis along y equals solve_lines on the transposed lines."""
+    f = np.random.default_rng(6).standard_normal((5, 12, 7))
+    bands = [0.25, 1.0, 0.25]
+    x = oracle.solve_axis(f, 1, bands)
+    lines = np.moveaxis(f, 1, 2).reshape(-1, 12)
+    ref = oracle.solve_lines(lines, bands).reshape(5, 7, 12)
+    assert np.abs(np.moveaxis(ref, 2, 1) - x).max() <= 1e-15
+
+
+def test_matvec_vs_dense():
+    f = np.random.default_rng(8).standard_normal((3, 4, 11))
+    bands = [0.05, 0.5, 1.0, 0.5, 0.05]
+    y = oracle.matvec_axis(f, 0, bands)
+    A = dense_matrix(bands, 11, True)
+    assert np.abs(y - f @ A.T).max() <= 1e-14
+
+
+# ----------------------------------------------------- closed forms (Eq. 1, 2)
+def modified_wavenumber(s, kh):
+    a, b, c = float(s["a"]), float(s["b"]), float(s.get("c", 0))
+    al, be = float(s["alpha"]), float(s.get("beta", 0))
+    return (a * np.sin(kh) + b / 2 * np.sin(2 * kh) + c / 3 * np.sin(3 * kh)) / (
+        1 + 2 * al * np.cos(kh) + 2 * be * np.cos(2 * kh))
+
+
+def modal_derivative(shape, modes, axis, s):
+    """d/dx_axis of sum A cos(k.x + phi) under the scheme's modified wavenumber."""
+    amp, k, phi = modes
+    nz, ny, nx = shape
+    n = shape[2 - axis]
+    h = 2 * np.pi / n
+    xs = [np.arange(m) * 2 * np.pi / m for m in (nx, ny, nz)]
+    X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")  # z, y, x
+    out = np.zeros(shape)
+    for m in range(len(amp)):
+        arg = k[m, 0] * X[2] + k[m, 1] * X[1] + k[m, 2] * X[0] + phi[m]
+        kp = modified_wavenumber(s, k[m, axis] * h) / h
+        out += -amp[m] * kp * np.sin(arg)
+    return out
+
+
+@pytest.mark.parametrize("name", ["deriv6", "deriv10"])
+def test_derivative_closed_form(name):
+    s = dict(deriv6=schemes.DERIV6, deriv10=schemes.DERIV10)[name]
+    shape = (24, 40, 32)
+    f, modes = synth.random_modes(shape, seed=11)
+    f = f.numpy()
+    bands = schemes.bands_collocated(s)
+    for axis in range(3):
+        n = shape[2 - axis]
+        lo, c = schemes.stencil_deriv_collocated(s, 2 * np.pi / n)
+        d = oracle.apply_axis(f, axis, bands, lo, c)
+        ref = modal_derivative(shape, modes, axis, s)
+        assert np.abs(d - ref).max() <= 1e-13 * np.abs(ref).max(), axis
+
+
+def test_derivative_converges_at_design_order():
+    """A single mode: error of the compact derivative vs the exact derivative
+    falls as h^6 (sixth order) and h^10 (tenth order)."""
+    for s, order in ((schemes.DERIV6, 6), (schemes.DERIV10, 10)):
+        errs = []
+        for n in (16, 32):
+            x = np.arange(n) * 2 * np.pi / n
+            f = np.sin(3 * x)[None, None, :]
+            lo, c = schemes.stencil_deriv_collocated(s, 2 * np.pi / n)
+            d = oracle.apply_axis(f, 0, schemes.bands_collocated(s), lo, c)[0, 0]
+            errs.append(np.abs(d - 3 * np.cos(3 * x)).max())
+        rate = math.log2(errs[0] / errs[1])
+        assert order - 0.5 < rate < order + 1.0, (order, rate)
+
+
+def test_interpolation_closed_form():
+    """Collocated -> staggered: f^I_j approximates f(x_{j+1/2}) with transfer
+    T(kh) = [a cos(kh/2) + b cos(3kh/2)] / [1 + 2 alpha cos(kh)]."""
+    s = schemes.INTERP6
+    shape = (16, 24, 32)
+    f, (amp, k, phi) = synth.random_modes(shape, seed=12)
+    f = f.numpy()
+    bands = [float(s["alpha"]), 1.0, float(s["alpha"])]
+    lo, c = schemes.stencil_interp_c2s(s)
+    for axis in range(3):
+        n = shape[2 - axis]
+        h = 2 * np.pi / n
+        out = oracle.apply_axis(f, axis, bands, lo, c)
+        xs = [np.arange(m) * 2 * np.pi / m for m in (shape[2], shape[1], shape[0])]
+        xs[axis] = xs[axis] + h / 2
+        X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        ref = np.zeros(shape)
+        for m in range(len(amp)):
+            kh = k[m, axis] * h
+            T = (float(s["a"]) * np.cos(kh / 2) + float(s["b"]) * np.cos(1.5 * kh)) / (
+                1 + 2 * float(s["alpha"]) * np.cos(kh))
+            ref += amp[m] * T * np.cos(k[m, 0] * X[2] + k[m, 1] * X[1] + k[m, 2] * X[0] + phi[m])
+        assert np.abs(out - ref).max() <= 1e-13, axis
+
+
+def test_staggered_derivative_closed_form():
+    """App. A.2 staggered derivative, collocated -> staggered points."""
+    s = schemes.STAG6
+    n = 48
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    lo, c = schemes.stencil_deriv_c2s(s, h)
+    for kk in (1, 5, 11):
+        f = np.cos(kk * x + 0.3)[None, None, :]
+        d = oracle.apply_axis(f, 0, [float(s["alpha"]), 1.0, float(s["alpha"])], lo, c)[0, 0]
+        kh = kk * h
+        kp = (2 * float(s["a"]) * np.sin(kh / 2) + 2 * float(s["b"]) / 3 * np.sin(1.5 * kh)) / (
+            1 + 2 * float(s["alpha"]) * np.cos(kh)) / h
+        ref = -kp * np.sin(kk * (x + h / 2) + 0.3)
+        assert np.abs(d - ref).max() <= 1e-13
+
+
+# --------------------------------------------- exact scheme coefficients ---
+def test_scheme_taylor_conditions_exact():
+    """Order conditions in exact rationals (Sec. 1 Eq. (1)-(2), App. A.2)."""
+    for s, P in ((schemes.DERIV6, 2), (schemes.DERIV10, 4)):
+        a, b, c, al, be = s["a"], s["b"], s["c"], s["alpha"], s["beta"]
+        assert a + b + c == 1 + 2 * al + 2 * be
+        for p in range(1, P + 1):
+            assert a + 4 ** p * b + 9 ** p * c == (2 * p + 1) * (2 * al + 2 * 4 ** p * be), p
+        p = P + 1  # and not one order more
+        assert a + 4 ** p * b + 9 ** p * c != (2 * p + 1) * (2 * al + 2 * 4 ** p * be)
+    s = schemes.INTERP6
+    assert s["a"] + s["b"] == 1 + 2 * s["alpha"]
+    for p in (1, 2):
+        assert (s["a"] + 9 ** p * s["b"]) / Fr(4) ** p == 2 * s["alpha"]
+    s = schemes.STAG6
+    assert s["a"] + s["b"] == 1 + 2 * s["alpha"]
+    for p in (1, 2):
+        assert (s["a"] + 9 ** p * s["b"]) / Fr(4) ** p == (2 * p + 1) * 2 * s["alpha"]
+
+
+def _golden_schemes():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "schemes_paper.txt")
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            name, q, val = line.split()[:3]
+            rows.append((name, q, Fr(val)))
+    return rows
+
+
+def test_scheme_values_match_paper():
+    """The oracle's coefficient table equals the values printed in the paper."""
+    table = dict(deriv6=schemes.DERIV6, interp6=schemes.INTERP6, stag6=schemes.STAG6)
+    rows = _golden_schemes()
+    assert len(rows) == 7
+    for name, q, val in rows:
+        assert table[name][q] == val, (name, q)
+
+
+# ------------------------------------------------- planted-mistake check ---
+MUTATIONS = [
+    # drop the Woodbury corner correction
+    ("x[i] -= op->z[k * n + i] * t[k];", "(void)0;"),
+    # mirror the band offsets (a transposed operand)
+    ("return bands[(per_row ? j * (2 * r + 1) : 0) + o + r];",
+     "return bands[(per_row ? j * (2 * r + 1) : 0) - o + r];"),
+    # stencil reads f_{j-q} instead of f_{j+q} (a sign of the index)
+    ("const int64_t jj = ((j + q) % n + n) % n;", "const int64_t jj = ((j - q) % n + n) % n;"),
+    # forward substitution skips its first coupling term (dropped term)
+    ("for (int j = j0; j < i; ++j) s -= lu[i * w + (j - i + r)] * x[j];",
+     "for (int j = j0 + 1; j < i; ++j) s -= lu[i * w + (j - i + r)] * x[j];"),
+    # corner rows mis-indexed (off by one)
+    ("op->crow[r + k] = n - r + k;", "op->crow[r + k] = n - r + k - 1;"),
+]
+
+
+@pytest.mark.parametrize("mi", range(len(MUTATIONS)))
+def test_pins_catch_planted_mistakes(mi, tmp_path, monkeypatch):
+    """Plant one mistake in a private copy of the oracle (CPU only) and check
+    that the pins above reject it."""
+    import ctypes
+    import os
+    import subprocess
+    from oracle import oracle as orc
+
+    src = open(os.path.join(os.path.dirname(orc.__file__), "cb_oracle.c")).read()
+    old, new = MUTATIONS[mi]
+    assert old in src
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", str(so), str(path)])
+    lib = ctypes.CDLL(str(so))
+    real = orc._load()
+    for name in ("orc_solve_lines", "orc_stencil_axis", "orc_solve_axis", "orc_apply_axis",
+                 "orc_matvec_axis"):
+        getattr(lib, name).argtypes = getattr(real, name).argtypes
+        getattr(lib, name).restype = ctypes.c_int
+    monkeypatch.setattr(orc, "_lib", lib)
+    checks = [
+        lambda: test_solve_vs_dense_lu(2, True, 16),
+        lambda: test_solve_vs_dense_lu(1, False, 11),
+        lambda: test_solve_vs_fft_circulant("deriv10", 256),
+        lambda: test_stencil_vs_dense_circulant(-2, [0.1, -0.7, 0.0, 0.7, -0.1]),
+        lambda: test_derivative_closed_form("deriv6"),
+    ]
+    failed = 0
+    for chk in checks:
+        try:
+            chk()
+        except (AssertionError, oracle.OracleError):
+            failed += 1
+    assert failed >= 1, "planted mistake %d went unnoticed" % mi
