@@ -1,0 +1,195 @@
+/*
+ * cb.h -- C ABI of libcb.so: batched solution of cyclic (or acyclic) compact
+ * banded systems A x = b by parallel cyclic reduction on AMD Instinct MI355X
+ * (gfx950), for compact finite-difference derivatives and interpolation along
+ * x, y or z of a 3D grid.
+ *
+ * Method (Song et al., "Scalable parallel linear solver for compact banded
+ * systems on heterogeneous architectures"):
+ *   - A has bandwidth w = 2r+1 (Sec. 2; r = 1 tridiagonal, r = 2
+ *     pentadiagonal) and is cyclic when the grid is periodic (Sec. 3).
+ *   - Each line is split into partitions; the first r rows of a partition are
+ *     its interface rows, the rest an acyclic banded block D_i (Sec. 3, the
+ *     partitioned system of Eqs. (7)-(8)).
+ *   - D_i y_i = b_i, D_i S_i = L_i, D_i R_i = U_i are solved by generalized
+ *     PCR (Sec. 2 Eqs. (3)-(6); Sec. 4 Eqs. (15)-(17)); the interface unknowns
+ *     form the reduced block system of Eqs. (18)-(21), solved by block PCR
+ *     with detach/reattach for sizes that are not powers of two (Sec. 3, the
+ *     11x11 example; Sec. 4, Algorithms 1-4); Eq. (22) back-substitutes.
+ *   - A is constant while b varies, so everything that does not depend on b
+ *     is computed once by cb_plan and kept on the device (Sec. 4, the
+ *     paragraph on pre-factorisation).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers (f, b, x, out) are DEVICE pointers to FP64 arrays owned
+ *     by the caller.  Host pointers (desc, bands, grid, stencil) are read
+ *     during the call only.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous with respect to the host: they enqueue kernels and return.
+ *   - Arguments are validated before anything is enqueued; on an error no
+ *     output is written, the call returns a non-zero cb_status and
+ *     cb_last_error() holds a message.  No C++ exception crosses the ABI.
+ *   - A plan may be used from several host threads and streams at once; it
+ *     is read-only after cb_plan returns.  Calls that write the same output
+ *     on different streams race, as any two kernels would.
+ */
+#ifndef CB_H
+#define CB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CB_OK = 0,
+  CB_ERR_INVALID_ARG = 1, /* bad pointer, size, axis, stride or descriptor */
+  CB_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+  CB_ERR_SINGULAR = 3,    /* cb_plan: a pivot or reduction system is singular */
+  CB_ERR_OOM = 4,         /* device allocation failed */
+  CB_ERR_HIP = 5          /* a HIP runtime call failed; see cb_last_error() */
+} cb_status;
+
+typedef enum {
+  CB_FP64 = 0,        /* every step in FP64 */
+  CB_FP32 = 1,        /* reduction arithmetic in FP32, FP64 input/output */
+  CB_FP32_REFINE = 2  /* FP32 reduction + FP64 residual iterative refinement */
+} cb_precision;
+
+typedef struct cb_plan_s *cb_plan_t;
+
+/* The problem statement A x = b (Sec. 2-3). */
+typedef struct {
+  int32_t r;             /* half bandwidth: 1 tridiagonal, 2 pentadiagonal (1..2) */
+  int32_t n;             /* system (line) length */
+  const double *bands;   /* HOST.  per_row = 0: 2r+1 values a_{-r..r}, row j reads
+                            A[j][j+o] = a_o.  per_row = 1: n*(2r+1) values,
+                            row-major [row][o+r].  Column indices wrap modulo n
+                            when cyclic; when acyclic, entries whose column
+                            falls outside [0,n) are ignored. */
+  int32_t per_row;       /* 0 constant coefficients, 1 per-row bands */
+  int32_t cyclic;        /* 1 periodic (corner blocks present), 0 acyclic */
+  int32_t partitions;    /* P >= 1 workgroup partitions per line (Sec. 3 p);
+                            P > 1 solves the reduced P-block system across
+                            workgroups (any P, detach/reattach when P is not a
+                            power of two).  0 = let the library choose (1). */
+  int32_t precision;     /* cb_precision */
+  int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations (0 -> 2) */
+  int32_t rows_per_lane; /* 0 = automatic; else 4, 6, 8, 12 or 16 */
+  int32_t host_only;     /* 1: factorise on the host only (no device memory is
+                            touched); such a plan can be inspected with
+                            cb_plan_get_* but solve calls reject it */
+} cb_plan_desc;
+
+/* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +
+ * i1*stride[1] + i2*stride[2]].  Index 0 is x.  A C-order (nz,ny,nx) array
+ * has n = {nx,ny,nz}, stride = {1,nx,nx*ny}.  Strides are in elements and
+ * must be positive; lines along `axis` have n[axis] == plan n. */
+typedef struct {
+  int64_t n[3];
+  int64_t stride[3];
+} cb_grid;
+
+/* A periodic right-hand-side stencil (Eq. (1)-(2), App. A.2):
+ *   b_j = sum_{q = lo}^{hi} coef[q - lo] * f_{(j + q) mod n}
+ * with -3 <= lo <= hi <= 3.  Derivative stencils fold 1/h into coef. */
+typedef struct {
+  int32_t lo;
+  int32_t hi;
+  double coef[7];
+} cb_stencil;
+
+/* Build a plan: the pre-factorisation of Sec. 4 in FP64 on the host,
+ * uploaded to the current HIP device.  Returns CB_ERR_SINGULAR when a pivot
+ * of a generalized-PCR reduction system or a reduced-system block is
+ * (numerically) singular.  *out receives the plan on success. */
+cb_status cb_plan(const cb_plan_desc *desc, cb_plan_t *out);
+
+/* Free a plan and its device buffers.  The caller must make sure no work
+ * using it is still pending.  NULL is accepted. */
+cb_status cb_plan_destroy(cb_plan_t plan);
+
+/* b = stencil(f) along `axis` (0 x, 1 y, 2 z), periodic wrap.  f and b are
+ * device arrays laid out by `grid`; they must not overlap. */
+cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t axis,
+                         const double *f, double *b, void *stream);
+
+/* x = A^{-1} b along `axis` for every line of the grid (Sec. 4, Algorithm 1
+ * applied to all lines at once).  b == x is allowed (in place); other
+ * overlaps are not. */
+cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b,
+                   double *x, void *stream);
+
+/* out = A^{-1} (stencil(f)) along `axis`: the compact derivative or
+ * interpolation with the stencil fused into the solve (b never goes to
+ * memory).  Requires a cyclic plan.  f and out must not overlap. */
+cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid,
+                              int32_t axis, const double *f, double *out, void *stream);
+
+/* One work item of a batched launch: a solve (stencil == NULL) or a fused
+ * derivative along one axis of one grid. */
+typedef struct {
+  cb_plan_t plan;
+  const cb_stencil *stencil; /* HOST pointer or NULL */
+  cb_grid grid;
+  int32_t axis;
+  const double *in;          /* device: b (solve) or f (derivative) */
+  double *out;               /* device */
+} cb_batch_item;
+
+/* Run many items in ONE persistent kernel launch over a device work table
+ * (lines of uneven grids share the launch).  All items must use plans of the
+ * same precision and half bandwidth r; items may differ in n, axis, grid and
+ * plan.  `workspace` is a device buffer of at least cb_batch_workspace_size()
+ * bytes, owned by the caller and not used concurrently by another call;
+ * `max_ctas` caps the number of resident workgroups (0 = one wave of the
+ * whole chip). */
+size_t cb_batch_workspace_size(int32_t n_items);
+cb_status cb_solve_batched(const cb_batch_item *items, int32_t n_items, void *workspace,
+                           size_t workspace_bytes, int32_t max_ctas, void *stream);
+
+/* Read-only description of a plan's decomposition, for tests and tuning. */
+typedef struct {
+  int32_t r, n, cyclic, precision, refine_iters;
+  int32_t partitions;      /* P workgroup partitions */
+  int32_t lanes;           /* L lanes (sub-partitions) per segment */
+  int32_t rows_per_lane;   /* M register slots per lane */
+  int32_t uniform;         /* 1: every lane partition identical */
+  int32_t interior_levels; /* generalized-PCR levels inside a lane partition */
+  int32_t lane_levels;     /* block-PCR levels across the lanes */
+  int32_t red_phases;      /* phases of the workgroup-level reduced solve */
+  int32_t red_pcr_steps;   /* block-PCR steps in it (Sec. 4 step counts) */
+  int32_t red_detach_steps;/* detach (= reattach) steps in it */
+  int64_t device_bytes;    /* device memory held by the plan */
+} cb_plan_info;
+cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
+
+/* Copy the detach schedule of the workgroup-level reduced solve: for each
+ * level, the (zero-based) rows detached at that level, -1 terminated per
+ * level.  Writes at most `cap` ints to `out`; returns the count in *len. */
+cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_t *len);
+
+/* Copy one host-side array of a plan (FP64 values; integer arrays are
+ * converted) for inspection by tests.  `seg` selects the segment (0 for a
+ * one-partition plan, else the workgroup partition).  which:
+ *   0 lane coefficient blocks [ntypes][block] (layout: k[Tint][N][2r],
+ *     dinv[N], Lt[r][r], Ut[r][r], S[N][r], Rm[N][r], N = M - r)
+ *   1 lane block-PCR multipliers [Tred][L][2][r][r] (MU then ML)
+ *   2 lane final blocks [L][r][r]
+ *   3 lane types [L]          4 lane starts [L+1]
+ *   5 workgroup S,R blocks (per partition [N_i][r] twice)
+ *   6 workgroup L~,U~ [P][2][r][r]   7 partition starts [P+1]
+ *   8 reduced-solve program: term ranges [phases][P+1]
+ *   9 its source rows per term          10 its matrices per term [r][r]
+ * Writes min(cap, size) values; *len receives the full size. */
+cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *out, int64_t cap,
+                            int64_t *len);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *cb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CB_H */

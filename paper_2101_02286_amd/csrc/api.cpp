@@ -1,0 +1,471 @@
+// C ABI of libcb: argument checking, plan upload, launch configuration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cb.h"
+#include "launch.h"
+#include "plan.h"
+
+struct cb_plan_s {
+  cb::Plan p;
+};
+
+namespace cb {
+namespace {
+
+thread_local std::string g_err;
+
+cb_status fail(cb_status s, const std::string &m) {
+  g_err = m;
+  return s;
+}
+
+cb_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return CB_ERR_HIP;
+}
+
+int ilog2(int v) {
+  int t = 0;
+  while ((1 << t) < v) ++t;
+  return t;
+}
+
+// --------------------------------------------------------- plan upload ----
+struct Arena {
+  std::vector<char> host;
+  size_t add(const void *src, size_t bytes) {
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + bytes);
+    if (bytes) std::memcpy(host.data() + off, src, bytes);
+    return off;
+  }
+  template <typename V> size_t add(const std::vector<V> &v) { return add(v.data(), v.size() * sizeof(V)); }
+};
+
+std::vector<float> to_f32(const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); }
+
+cb_status upload(Plan &p) {
+  Arena ar;
+  struct SegOff { size_t lt, ls, c64, r64, w64, c32, r32, w32; };
+  std::vector<SegOff> so(p.segs.size());
+  for (size_t i = 0; i < p.segs.size(); ++i) {
+    const SegPlan &s = p.segs[i];
+    so[i].lt = ar.add(s.lane_type);
+    so[i].ls = ar.add(s.lane_start);
+    so[i].c64 = ar.add(s.coef);
+    so[i].r64 = ar.add(s.red);
+    so[i].w64 = ar.add(s.wf);
+    so[i].c32 = ar.add(to_f32(s.coef));
+    so[i].r32 = ar.add(to_f32(s.red));
+    so[i].w32 = ar.add(to_f32(s.wf));
+  }
+  const size_t o_bands = ar.add(p.bands);
+  size_t o_wg = 0, o_sr = 0, o_sroff = 0, o_ltut = 0, o_ro = 0, o_src = 0, o_mats = 0;
+  if (p.P > 1) {
+    o_wg = ar.add(p.wg_start);
+    o_sr = ar.add(p.SRg);
+    o_sroff = ar.add(p.SRg_off);
+    o_ltut = ar.add(p.LtUtg);
+    o_ro = ar.add(p.prog.row_off);
+    o_src = ar.add(p.prog.src);
+    o_mats = ar.add(p.prog.mats);
+  }
+  const size_t o_segdev = ar.add(nullptr, sizeof(SegDev) * p.segs.size());
+  void *d = nullptr;
+  hipError_t e = hipMalloc(&d, ar.host.size());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? fail(CB_ERR_OOM, "cb_plan: device allocation failed")
+                                    : hip_fail(e, "cb_plan: hipMalloc");
+  }
+  char *base = static_cast<char *>(d);
+  p.segdev_host.resize(p.segs.size());
+  for (size_t i = 0; i < p.segs.size(); ++i) {
+    const SegPlan &s = p.segs[i];
+    SegDev &g = p.segdev_host[i];
+    g.S = s.S;
+    g.L = s.L;
+    g.M = s.M;
+    g.Tint = s.Tint;
+    g.Tred = s.Tred;
+    g.uniform = s.uniform;
+    g.m = s.m_uniform;
+    g.block = s.block;
+    g.lane_type = reinterpret_cast<const int *>(base + so[i].lt);
+    g.lane_start = reinterpret_cast<const int *>(base + so[i].ls);
+    g.coef64 = reinterpret_cast<const double *>(base + so[i].c64);
+    g.red64 = reinterpret_cast<const double *>(base + so[i].r64);
+    g.wf64 = reinterpret_cast<const double *>(base + so[i].w64);
+    g.coef32 = reinterpret_cast<const float *>(base + so[i].c32);
+    g.red32 = reinterpret_cast<const float *>(base + so[i].r32);
+    g.wf32 = reinterpret_cast<const float *>(base + so[i].w32);
+  }
+  std::memcpy(ar.host.data() + o_segdev, p.segdev_host.data(), sizeof(SegDev) * p.segs.size());
+  e = hipMemcpy(d, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "cb_plan: hipMemcpy");
+  }
+  p.dev_base = d;
+  p.dev_bytes = (int64_t)ar.host.size();
+  p.segdev = reinterpret_cast<SegDev *>(base + o_segdev);
+  p.d_bands = reinterpret_cast<const double *>(base + o_bands);
+  if (p.P > 1) {
+    p.d_wg_start = reinterpret_cast<const int *>(base + o_wg);
+    p.d_SRg = reinterpret_cast<const double *>(base + o_sr);
+    p.d_SRg_off = reinterpret_cast<const int64_t *>(base + o_sroff);
+    p.d_LtUtg = reinterpret_cast<const double *>(base + o_ltut);
+    p.d_row_off = reinterpret_cast<const int *>(base + o_ro);
+    p.d_src = reinterpret_cast<const int *>(base + o_src);
+    p.d_mats = reinterpret_cast<const double *>(base + o_mats);
+  }
+  return CB_OK;
+}
+
+// ------------------------------------------------------- geometry checks --
+struct Geo {
+  int64_t n, nu, su, sv, rs, nlines;
+};
+
+cb_status geometry(const cb_grid *g, int axis, Geo &o) {
+  if (!g) return fail(CB_ERR_INVALID_ARG, "grid is NULL");
+  if (axis < 0 || axis > 2) return fail(CB_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
+  for (int i = 0; i < 3; ++i)
+    if (g->n[i] <= 0 || g->stride[i] <= 0)
+      return fail(CB_ERR_INVALID_ARG, "grid extents and strides must be positive");
+  const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
+  o.n = g->n[axis];
+  o.rs = g->stride[axis];
+  o.nu = g->n[u];
+  o.su = g->stride[u];
+  o.sv = g->stride[v];
+  o.nlines = g->n[u] * g->n[v];
+  return CB_OK;
+}
+
+int64_t span_elems(const cb_grid *g) {
+  int64_t s = 1;
+  for (int i = 0; i < 3; ++i) s += (g->n[i] - 1) * g->stride[i];
+  return s;
+}
+
+bool overlap(const void *a, const void *b, int64_t elems) {
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  const int64_t bytes = elems * 8;
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+void stencil_q(const cb_stencil *st, double out[7]) {
+  for (int i = 0; i < 7; ++i) out[i] = 0.0;
+  for (int q = st->lo; q <= st->hi; ++q) out[q + 3] = st->coef[q - st->lo];
+}
+
+cb_status check_stencil(const cb_stencil *st) {
+  if (!st) return fail(CB_ERR_INVALID_ARG, "stencil is NULL");
+  if (st->lo < -3 || st->hi > 3 || st->lo > st->hi)
+    return fail(CB_ERR_INVALID_ARG, "stencil offsets must satisfy -3 <= lo <= hi <= 3");
+  return CB_OK;
+}
+
+// --------------------------------------------------------- P = 1 launch --
+cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
+                      hipStream_t stream) {
+  const SegPlan &sp = p.segs[0];
+  const bool uni = sp.uniform != 0;
+  const int Q = st ? 3 : 0;
+  const bool fp32 = p.precision != CB_FP64;
+  // MODE_X needs unit row stride; the vectorised uniform path also needs
+  // 16-byte aligned line starts.
+  int mode = (g.rs == 1) ? MODE_X : MODE_S;
+  if (mode == MODE_X && uni) {
+    const bool al = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
+                    (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
+    if (!al) mode = MODE_S;
+  }
+  const void *fn = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni);
+  if (!fn) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
+  const int L = sp.L;
+  int NT;
+  if (mode == MODE_X) {
+    NT = std::max(L, 256);
+  } else {
+    NT = std::min(1024, std::max(L, 16 * L));
+  }
+  NT = std::min(NT, 1024);
+  if (L > 1024) return fail(CB_ERR_UNSUPPORTED, "line needs more than 1024 lanes");
+  const int W = NT / L;
+  LineArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.nlines = g.nlines;
+  a.nu = g.nu;
+  a.su = g.su;
+  a.sv = g.sv;
+  a.rs = g.rs;
+  a.lgL = ilog2(L);
+  a.lgW = ilog2(W);
+  a.block_sync = 1;
+  a.refine_iters = p.refine_iters;
+  a.seg = p.segdev_host[0];
+  if (st) stencil_q(st, a.stc);
+  for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
+  a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
+  const int RS = std::max(Q, p.R);
+  const size_t lds = (size_t)NT * 2 * RS * sizeof(double);
+  const int64_t blocks = (g.nlines + W - 1) / W;
+  if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(NT), args, lds, stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return CB_OK;
+}
+
+// --------------------------------------------------------- P > 1 launch --
+cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, hipStream_t stream) {
+  int mode = (g.rs == 1) ? MODE_X : MODE_S;
+  const WgKernel *k = find_wg_kernel(p.R, p.M, mode);
+  if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
+  const int L = p.L;
+  int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
+  NT = std::min(std::max(NT, L), 1024);
+  const int W = NT / L;
+  WgArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.out = out;
+  a.nlines = g.nlines;
+  a.nu = g.nu;
+  a.su = g.su;
+  a.sv = g.sv;
+  a.rs = g.rs;
+  a.lgL = ilog2(L);
+  a.lgW = ilog2(W);
+  a.P = p.P;
+  a.nphase = p.prog.nphase;
+  a.segs = p.segdev;
+  a.wg_start = p.d_wg_start;
+  a.SR = p.d_SRg;
+  a.SR_off = p.d_SRg_off;
+  a.LtUt = p.d_LtUtg;
+  a.row_off = p.d_row_off;
+  a.src = p.d_src;
+  a.mats = p.d_mats;
+  const size_t sbytes = (size_t)g.nlines * p.P * 3 * p.R * sizeof(double);
+  void *scratch = nullptr;
+  hipError_t e = hipMallocAsync(&scratch, std::max<size_t>(sbytes, 256), stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
+  }
+  a.scratch = static_cast<double *>(scratch);
+  const int64_t tiles = (g.nlines + W - 1) / W;
+  dim3 grid((unsigned)tiles, (unsigned)p.P);
+  void *args[] = {&a};
+  const size_t lds_a = (size_t)NT * 2 * p.R * sizeof(double);
+  const size_t lds_c = lds_a + (size_t)2 * W * p.P * p.R * sizeof(double);
+  e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
+  if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
+  hipError_t e2 = hipFreeAsync(scratch, stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return CB_OK;
+}
+
+cb_status check_plan_for_solve(cb_plan_t plan) {
+  if (!plan) return fail(CB_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->p.host_only || !plan->p.dev_base)
+    return fail(CB_ERR_INVALID_ARG, "plan was built host-only");
+  return CB_OK;
+}
+
+}  // namespace
+}  // namespace cb
+
+using namespace cb;
+
+extern "C" {
+
+cb_status cb_plan(const cb_plan_desc *desc, cb_plan_t *out) {
+  try {
+    if (!desc || !out) return fail(CB_ERR_INVALID_ARG, "desc and out must be non-NULL");
+    *out = nullptr;
+    cb_plan_s *h = new (std::nothrow) cb_plan_s();
+    if (!h) return fail(CB_ERR_OOM, "host allocation failed");
+    std::string msg;
+    cb_status s = build_plan(*desc, h->p, msg);
+    if (s != CB_OK) {
+      delete h;
+      return fail(s, "cb_plan: " + msg);
+    }
+    h->p.host_only = desc->host_only;
+    if (!desc->host_only) {
+      s = upload(h->p);
+      if (s != CB_OK) {
+        delete h;
+        return s;
+      }
+    }
+    *out = h;
+    g_err.clear();
+    return CB_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(CB_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(CB_ERR_INVALID_ARG, "cb_plan: unexpected error");
+  }
+}
+
+cb_status cb_plan_destroy(cb_plan_t plan) {
+  if (!plan) return CB_OK;
+  cb_status s = CB_OK;
+  if (plan->p.dev_base) {
+    hipError_t e = hipFree(plan->p.dev_base);
+    if (e != hipSuccess) s = hip_fail(e, "cb_plan_destroy: hipFree");
+  }
+  delete plan;
+  return s;
+}
+
+cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t axis, const double *f,
+                         double *b, void *stream) {
+  cb_status s = check_stencil(stencil);
+  if (s) return s;
+  Geo g;
+  if ((s = geometry(grid, axis, g))) return s;
+  if (!f || !b) return fail(CB_ERR_INVALID_ARG, "f and b must be non-NULL");
+  if (overlap(f, b, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and b overlap");
+  StencilArgs a;
+  a.f = f;
+  a.b = b;
+  a.n = g.n;
+  a.nu = g.nu;
+  a.su = g.su;
+  a.sv = g.sv;
+  a.rs = g.rs;
+  a.total = g.nlines * g.n;
+  a.lo = stencil->lo;
+  a.hi = stencil->hi;
+  for (int i = 0; i < 7; ++i) a.c[i] = i <= stencil->hi - stencil->lo ? stencil->coef[i] : 0.0;
+  const int64_t blocks = (a.total + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "grid too large for one launch");
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(stencil_kernel(), dim3((unsigned)blocks), dim3(256), args, 0,
+                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return CB_OK;
+}
+
+cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b, double *x,
+                   void *stream) {
+  cb_status s = check_plan_for_solve(plan);
+  if (s) return s;
+  Geo g;
+  if ((s = geometry(grid, axis, g))) return s;
+  if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (!b || !x) return fail(CB_ERR_INVALID_ARG, "b and x must be non-NULL");
+  if (b != x && overlap(b, x, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "b and x overlap");
+  if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
+  if (plan->p.precision != CB_FP64)
+    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
+  return launch_wg(plan->p, g, b, x, static_cast<hipStream_t>(stream));
+}
+
+cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid, int32_t axis,
+                              const double *f, double *out, void *stream) {
+  cb_status s = check_plan_for_solve(plan);
+  if (s) return s;
+  if ((s = check_stencil(stencil))) return s;
+  Geo g;
+  if ((s = geometry(grid, axis, g))) return s;
+  if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (!f || !out) return fail(CB_ERR_INVALID_ARG, "f and out must be non-NULL");
+  if (overlap(f, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and out overlap");
+  if (!plan->p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "the fused stencil needs a cyclic plan");
+  if (plan->p.P != 1) return fail(CB_ERR_UNSUPPORTED, "fused stencil with P > 1 partitions");
+  return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
+}
+
+size_t cb_batch_workspace_size(int32_t n_items) { return n_items > 0 ? (size_t)n_items * 256 + 256 : 256; }
+
+cb_status cb_solve_batched(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
+                           int32_t max_ctas, void *stream) {
+  (void)items;
+  (void)n_items;
+  (void)workspace;
+  (void)workspace_bytes;
+  (void)max_ctas;
+  (void)stream;
+  return fail(CB_ERR_UNSUPPORTED, "cb_solve_batched: not built yet");
+}
+
+cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
+  if (!plan || !info) return fail(CB_ERR_INVALID_ARG, "plan and info must be non-NULL");
+  const Plan &p = plan->p;
+  std::memset(info, 0, sizeof(*info));
+  info->r = p.R;
+  info->n = p.n;
+  info->cyclic = p.desc.cyclic;
+  info->precision = p.precision;
+  info->refine_iters = p.refine_iters;
+  info->partitions = p.P;
+  info->lanes = p.L;
+  info->rows_per_lane = p.M;
+  info->uniform = p.segs.empty() ? 0 : p.segs[0].uniform;
+  info->interior_levels = p.segs.empty() ? 0 : p.segs[0].Tint;
+  info->lane_levels = p.segs.empty() ? 0 : p.segs[0].Tred;
+  info->red_phases = p.prog.nphase;
+  info->red_pcr_steps = p.prog.pcr_steps;
+  info->red_detach_steps = p.prog.detach_steps;
+  info->device_bytes = p.dev_bytes;
+  return CB_OK;
+}
+
+cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_t *len) {
+  if (!plan || !len) return fail(CB_ERR_INVALID_ARG, "plan and len must be non-NULL");
+  std::vector<int32_t> v;
+  for (const auto &lvl : plan->p.prog.detached) {
+    for (int d : lvl) v.push_back(d);
+    v.push_back(-1);
+  }
+  *len = (int32_t)v.size();
+  if (out)
+    for (int32_t i = 0; i < std::min<int32_t>(cap, (int32_t)v.size()); ++i) out[i] = v[i];
+  return CB_OK;
+}
+
+cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *out, int64_t cap, int64_t *len) {
+  if (!plan || !len) return fail(CB_ERR_INVALID_ARG, "plan and len must be non-NULL");
+  const Plan &p = plan->p;
+  if (seg < 0 || seg >= (int32_t)p.segs.size()) return fail(CB_ERR_INVALID_ARG, "segment index out of range");
+  const SegPlan &s = p.segs[seg];
+  std::vector<double> v;
+  switch (which) {
+    case 0: v = s.coef; break;
+    case 1: v = s.red; break;
+    case 2: v = s.wf; break;
+    case 3: v.assign(s.lane_type.begin(), s.lane_type.end()); break;
+    case 4: v.assign(s.lane_start.begin(), s.lane_start.end()); break;
+    case 5: v = p.SRg; break;
+    case 6: v = p.LtUtg; break;
+    case 7: v.assign(p.wg_start.begin(), p.wg_start.end()); break;
+    case 8: v.assign(p.prog.row_off.begin(), p.prog.row_off.end()); break;
+    case 9: v.assign(p.prog.src.begin(), p.prog.src.end()); break;
+    case 10: v = p.prog.mats; break;
+    default: return fail(CB_ERR_INVALID_ARG, "unknown array id");
+  }
+  *len = (int64_t)v.size();
+  if (out) std::memcpy(out, v.data(), sizeof(double) * (size_t)std::min<int64_t>(cap, (int64_t)v.size()));
+  return CB_OK;
+}
+
+const char *cb_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Device-side building blocks of the line solver (gfx950).
+//
+// Mapping of the paper's two-level factorisation onto a workgroup:
+//   * a line (or a workgroup partition's interior block) is a "segment" of S
+//     rows split over L lanes; lane l owns m_l <= M consecutive rows in
+//     registers.  Lanes play the role of the paper's partitions: the first R
+//     rows of a lane are its interface rows, the rest its interior block D_l
+//     (Sec. 3, Eqs. (7)-(8)).
+//   * D_l y_l = b_l is solved in registers by generalized PCR with the
+//     plan's stored multipliers (Sec. 2 Eq. (3); Sec. 4 Eq. (17)).
+//   * The interface right-hand side b^_l (Eq. (21)) needs only the last R
+//     rows of y_{l-1} (the sparsity of L~), exchanged through LDS.
+//   * The reduced cyclic block system across the L lanes is solved by block
+//     PCR (Algorithm 3), each level exchanging R values with lanes l+-s.
+//   * Back-substitution x_l = y_l - S_l x~_l - R_l x~_{l+1} (Eq. (22)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "launch.h"
+#include "plan.h"
+
+namespace cb {
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+constexpr int ceil_log2_c(int v) { return v <= 1 ? 0 : 1 + ceil_log2_c((v + 1) / 2); }
+
+template <typename T> __device__ __forceinline__ const T *coef_of(const SegDev &s);
+template <> __device__ __forceinline__ const double *coef_of<double>(const SegDev &s) { return s.coef64; }
+template <> __device__ __forceinline__ const float *coef_of<float>(const SegDev &s) { return s.coef32; }
+template <typename T> __device__ __forceinline__ const T *red_of(const SegDev &s);
+template <> __device__ __forceinline__ const double *red_of<double>(const SegDev &s) { return s.red64; }
+template <> __device__ __forceinline__ const float *red_of<float>(const SegDev &s) { return s.red32; }
+template <typename T> __device__ __forceinline__ const T *wf_of(const SegDev &s);
+template <> __device__ __forceinline__ const double *wf_of<double>(const SegDev &s) { return s.wf64; }
+template <> __device__ __forceinline__ const float *wf_of<float>(const SegDev &s) { return s.wf32; }
+
+// LDS exchange between the lanes of one line.  Each thread owns two regions
+// of RS doubles; exchange number k writes region k&1, waits at a barrier, and
+// reads partners' region k&1.  Exchange k+2 reuses the region only after the
+// barrier of exchange k+1, which every thread reaches after its reads of
+// exchange k, so one barrier per exchange suffices.
+struct Xchg {
+  double *base;  // LDS, NT * 2 * RS doubles
+  int RS;        // doubles per region
+  int NT;
+  int k;         // exchange counter
+  bool block_sync;
+  __device__ __forceinline__ void sync() {
+    if (block_sync) {
+      __syncthreads();
+    } else {
+      // all lanes of every line are in this wave: LDS traffic of a wave is
+      // processed in order, only the compiler must not reorder it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __device__ __forceinline__ double *slot(int tid) { return base + ((size_t)tid * 2 + (k & 1)) * RS; }
+  template <int CNT, typename V>
+  __device__ __forceinline__ void publish(int tid, const V (&vals)[CNT]) {
+    double *p = slot(tid);
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) p[i] = (double)vals[i];
+    sync();
+  }
+  template <int CNT, typename V>
+  __device__ __forceinline__ void fetch(int tid_src, V (&out)[CNT]) {
+    const double *p = slot(tid_src);
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) out[i] = (V)p[i];
+  }
+  __device__ __forceinline__ void done() { ++k; }
+};
+
+// Position of this thread: lane l of line li inside a tile of W lines.
+struct LanePos {
+  int tid, l, li, L, W, lgL, lgW, mode;
+  __device__ __forceinline__ int tid_of(int lane) const {
+    return mode == MODE_X ? (li << lgL) + lane : (lane << lgW) + li;
+  }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ T select_idx(const T (&y)[N], int idx) {
+  T r = (T)0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) r = (j == idx) ? y[j] : r;
+  return r;
+}
+
+// Solve the segment in place: on entry v[0..m) holds b of the lane's rows, on
+// exit x.  Padding slots (k >= m) hold zero and stay zero.
+template <int R, int M, typename T, bool UNI>
+__device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const LanePos &p, int type,
+                                              int m, Xchg &xc) {
+  constexpr int N = M - R;
+  constexpr int TI = ceil_log2_c(N);
+  constexpr int RR = R * R;
+  constexpr CoefOff off = coef_offsets(R, M, TI);
+  const T *cf = coef_of<T>(sg) + (size_t)(UNI ? 0 : type) * sg.block;
+
+  // ---- interior generalized PCR, D_l y = b (Eq. (3) with stored k) ----
+  T y[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) y[j] = v[R + j];
+#pragma unroll
+  for (int t = 0; t < TI; ++t) {
+    const int s = 1 << t;
+    T yn[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T acc = y[j];
+      const T *kj = cf + off.k + (t * N + j) * 2 * R;
+#pragma unroll
+      for (int q = 1; q <= R; ++q) {
+        if (j - q * s >= 0) acc -= kj[R - q] * y[j - q * s];
+        if (j + q * s < N) acc -= kj[R + q - 1] * y[j + q * s];
+      }
+      yn[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) y[j] = yn[j];
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) y[j] *= cf[off.dinv + j];
+
+  // ---- interface RHS b^_l = b~_l - L~_l y_{l-1} - U~_l y_l (Eq. (21)) ----
+  const int nl = m - R;  // real interior rows of this lane
+  T ylast[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) ylast[a] = UNI ? y[N - R + a] : select_idx(y, nl - R + a);
+  xc.publish(p.tid, ylast);
+  T yprev[R];
+  xc.fetch(p.tid_of((p.l - 1) & (p.L - 1)), yprev);
+  xc.done();
+  T xt[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    T acc = v[a];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc -= cf[off.Lt + a * R + c] * yprev[c] + cf[off.Ut + a * R + c] * y[c];
+    xt[a] = acc;
+  }
+
+  // ---- reduced cyclic block system across lanes: block PCR (Alg. 3) ----
+  const T *rd = red_of<T>(sg);
+  const int lr = UNI ? 0 : p.l;
+  for (int t = 0; t < sg.Tred; ++t) {
+    const int s = 1 << t;
+    xc.publish(p.tid, xt);
+    T xp[R], xm[R];
+    xc.fetch(p.tid_of((p.l + s) & (p.L - 1)), xp);
+    xc.fetch(p.tid_of((p.l - s) & (p.L - 1)), xm);
+    xc.done();
+    const T *mu = rd + ((size_t)(t * sg.L + lr) * 2) * RR;
+    const T *ml = mu + RR;
+    T xn[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      T acc = xt[a];
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc -= mu[a * R + c] * xp[c] + ml[a * R + c] * xm[c];
+      xn[a] = acc;
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a) xt[a] = xn[a];
+  }
+  {
+    const T *w = wf_of<T>(sg) + (size_t)lr * RR;
+    T xn[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      T acc = (T)0;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc += w[a * R + c] * xt[c];
+      xn[a] = acc;
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a) xt[a] = xn[a];
+  }
+
+  // ---- back-substitution x_l = y_l - S_l x~_l - R_l x~_{l+1} (Eq. (22)) ----
+  xc.publish(p.tid, xt);
+  T xnext[R];
+  xc.fetch(p.tid_of((p.l + 1) & (p.L - 1)), xnext);
+  xc.done();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T acc = y[j];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      acc -= cf[off.S + j * R + c] * xt[c] + cf[off.Rm + j * R + c] * xnext[c];
+    v[R + j] = acc;
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) v[a] = xt[a];
+}
+
+// Halo exchange of the Q rows on each side of the lane (periodic through the
+// lanes of a cyclic segment): prev[i] = row start-Q+i, next[i] = row start+m+i.
+template <int Q, int M, typename V>
+__device__ __forceinline__ void halo(const V (&v)[M], int m, bool full, const LanePos &p, Xchg &xc,
+                                     V (&prev)[Q], V (&next)[Q]) {
+  V out[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (full) {
+      out[i] = v[M - Q + i];
+    } else {
+      V r = (V)0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) r = (j == m - Q + i) ? v[j] : r;
+      out[i] = r;
+    }
+  }
+  xc.publish(p.tid, out);
+  xc.fetch(p.tid_of((p.l - 1) & (p.L - 1)), prev);
+  xc.done();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i] = v[i];
+  xc.publish(p.tid, out);
+  xc.fetch(p.tid_of((p.l + 1) & (p.L - 1)), next);
+  xc.done();
+}
+
+// Value of row (k + q) relative to the lane start, from registers or halos.
+template <int Q, int M, typename V>
+__device__ __forceinline__ V row_at(const V (&v)[M], const V (&prev)[Q], const V (&next)[Q], int idx,
+                                    int m, bool full) {
+  if (idx < 0) return prev[Q + idx];
+  if (full) return idx < M ? v[idx] : next[idx - M];
+  if (idx >= M) return select_idx(next, idx - m);
+  return idx < m ? v[idx] : select_idx(next, idx - m);
+}
+
+}  // namespace cb

@@ -1,0 +1,369 @@
+// HIP kernels of libcb for gfx950 (MI355X) and their launchers.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "device.h"
+#include "launch.h"
+
+namespace cb {
+
+// ------------------------------------------------------------------------
+// Line solver for one-partition lines (P = 1): load -> [stencil] -> solve
+// [-> FP64 residual refinement] -> store, all on chip.  One workgroup per
+// tile of W lines; the L lanes of a line hold its rows in registers.
+// MODE_X: rows of a line are contiguous (unit stride); a line's lanes are
+//         adjacent threads.  MODE_S: strided rows; threads of equal lane
+//         index cover W adjacent lines so each row access is one contiguous
+//         W*8-byte segment.
+// ------------------------------------------------------------------------
+template <int R, int M, typename T, int MODE, int Q, bool UNI>
+__global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
+  extern __shared__ double smem[];
+  constexpr int RS = (Q > R ? Q : R);
+  LanePos p;
+  p.tid = threadIdx.x;
+  p.lgL = a.lgL;
+  p.lgW = a.lgW;
+  p.L = 1 << a.lgL;
+  p.W = 1 << a.lgW;
+  p.mode = MODE;
+  if (MODE == MODE_X) {
+    p.li = p.tid >> p.lgL;
+    p.l = p.tid & (p.L - 1);
+  } else {
+    p.l = p.tid >> p.lgW;
+    p.li = p.tid & (p.W - 1);
+  }
+  Xchg xc{smem, RS, (int)blockDim.x, 0, a.block_sync != 0};
+  const SegDev &sg = a.seg;
+  const int64_t line = (int64_t)blockIdx.x * p.W + p.li;
+  const bool active = line < a.nlines;
+  const int64_t lu = active ? line % a.nu : 0, lv = active ? line / a.nu : 0;
+  const int64_t base = lu * a.su + lv * a.sv;
+  int start, m, type = 0;
+  if (UNI) {
+    m = M;
+    start = p.l * M;
+  } else {
+    start = sg.lane_start[p.l];
+    m = sg.lane_start[p.l + 1] - start;
+    type = sg.lane_type[p.l];
+  }
+  const int64_t rs = MODE == MODE_X ? 1 : a.rs;
+  const double *in = a.in + base + start * rs;
+  double *out = a.out + base + start * rs;
+
+  double b64[M];
+  if (MODE == MODE_X && UNI && (M % 2 == 0)) {
+    const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) {
+      dbl2 t = active ? __builtin_nontemporal_load(in2 + k) : dbl2{0.0, 0.0};
+      b64[2 * k] = t.x;
+      b64[2 * k + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? __builtin_nontemporal_load(in + k * rs) : 0.0;
+  }
+
+  if (Q > 0) {  // fused right-hand-side stencil (Eq. (1)/(2)), periodic
+    double fp[Q > 0 ? Q : 1], fn[Q > 0 ? Q : 1];
+    halo<(Q > 0 ? Q : 1), M>(b64, m, UNI, p, xc, fp, fn);
+    double bb[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = -Q; q <= Q; ++q) acc += a.stc[q + Q] * row_at<(Q > 0 ? Q : 1), M>(b64, fp, fn, k + q, m, UNI);
+      bb[k] = (UNI || k < m) ? acc : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = bb[k];
+  }
+
+  double x64[M];
+  if (sizeof(T) == 8) {
+    T v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
+    solve_segment<R, M, T, UNI>(v, sg, p, type, m, xc);
+#pragma unroll
+    for (int k = 0; k < M; ++k) x64[k] = (double)v[k];
+  } else {
+    // FP32 reduction with FP64 residual refinement: x <- x + A32^{-1}(b - A x)
+#pragma unroll
+    for (int k = 0; k < M; ++k) x64[k] = 0.0;
+    for (int it = 0; it <= a.refine_iters; ++it) {
+      T v[M];
+      if (it == 0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
+      } else {
+        double xp[R], xn[R];
+        halo<R, M>(x64, m, UNI, p, xc, xp, xn);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          v[k] = (T)0;
+          if (UNI || k < m) {  // padding slots (k >= m) have no row
+            double ax = 0.0;
+            const double *bd = a.bands_row ? a.bands_row + (int64_t)(start + k) * (2 * R + 1) : a.bands;
+#pragma unroll
+            for (int o = -R; o <= R; ++o) ax += bd[o + R] * row_at<R, M>(x64, xp, xn, k + o, m, UNI);
+            v[k] = (T)(b64[k] - ax);
+          }
+        }
+      }
+      solve_segment<R, M, T, UNI>(v, sg, p, type, m, xc);
+#pragma unroll
+      for (int k = 0; k < M; ++k) x64[k] += (double)v[k];
+    }
+  }
+
+  if (!active) return;
+  if (MODE == MODE_X && UNI && (M % 2 == 0)) {
+    dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) __builtin_nontemporal_store(dbl2{x64[2 * k], x64[2 * k + 1]}, out2 + k);
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (UNI || k < m) __builtin_nontemporal_store(x64[k], out + k * rs);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Lines split over P > 1 workgroup partitions (Sec. 3-4 with workgroups as
+// partitions).  Phase A: y_i = D_i^{-1} b_i on each partition; the interface
+// RHS b~_i and the first/last R rows of y_i go to a small scratch array (the
+// only data a partition shares, Sec. 4 on the sparsity of L~ and U~).
+// Phase C: every workgroup of a line assembles b^ (Eq. (21)), solves the
+// P-block reduced system (Algorithm 1's level loop with detach/reattach,
+// precomputed as a program of phases), recomputes y_i and back-substitutes
+// (Eq. (22)).
+// ------------------------------------------------------------------------
+template <int R, int M, int MODE>
+__device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &line, bool &active,
+                                         int64_t &base) {
+  p.tid = threadIdx.x;
+  p.lgL = a.lgL;
+  p.lgW = a.lgW;
+  p.L = 1 << a.lgL;
+  p.W = 1 << a.lgW;
+  p.mode = MODE;
+  if (MODE == MODE_X) {
+    p.li = p.tid >> p.lgL;
+    p.l = p.tid & (p.L - 1);
+  } else {
+    p.l = p.tid >> p.lgW;
+    p.li = p.tid & (p.W - 1);
+  }
+  line = (int64_t)blockIdx.x * p.W + p.li;
+  active = line < a.nlines;
+  const int64_t lu = active ? line % a.nu : 0, lv = active ? line / a.nu : 0;
+  base = lu * a.su + lv * a.sv;
+}
+
+template <int R, int M, int MODE>
+__device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
+                                                  int64_t base, int part, Xchg &xc, double (&v)[M],
+                                                  int &start, int &m) {
+  const SegDev &sg = a.segs[part];
+  start = sg.lane_start[p.l];
+  m = sg.lane_start[p.l + 1] - start;
+  const int type = sg.lane_type[p.l];
+  const int64_t row0 = a.wg_start[part] + R + start;
+  const double *in = a.in + base + row0 * a.rs;
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
+  solve_segment<R, M, double, false>(v, sg, p, type, m, xc);
+}
+
+template <int R, int M, int MODE>
+__global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
+  extern __shared__ double smem[];
+  LanePos p;
+  int64_t line, base;
+  bool active;
+  wg_setup<R, M, MODE>(a, p, line, active, base);
+  Xchg xc{smem, R, (int)blockDim.x, 0, true};
+  const int part = blockIdx.y;
+  double v[M];
+  int start, m;
+  wg_solve_interior<R, M, MODE>(a, p, active, base, part, xc, v, start, m);
+  if (!active) return;
+  double *sc = a.scratch + (line * a.P + part) * 3 * R;
+  if (p.l == 0) {
+    const int64_t g0 = a.wg_start[part];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      sc[c] = a.in[base + (g0 + c) * a.rs];  // b~_i
+      sc[R + c] = v[c];                      // first R rows of y_i
+    }
+  }
+  if (p.l == p.L - 1) {
+    const int nl = m;
+#pragma unroll
+    for (int c = 0; c < R; ++c) sc[2 * R + c] = select_idx(v, nl - R + c);  // last R rows of y_i
+  }
+}
+
+template <int R, int M, int MODE>
+__global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
+  extern __shared__ double smem[];
+  LanePos p;
+  int64_t line, base;
+  bool active;
+  wg_setup<R, M, MODE>(a, p, line, active, base);
+  const int P = a.P, part = blockIdx.y, NT = blockDim.x;
+  // reduced-system state in LDS: two buffers of [W][P][R], after the lane
+  // exchange area
+  double *xr0 = smem + (size_t)NT * 2 * R;
+  double *xr1 = xr0 + (size_t)p.W * P * R;
+  const int64_t tile0 = (int64_t)blockIdx.x * p.W;
+  for (int idx = p.tid; idx < p.W * P; idx += NT) {
+    const int li = idx / P, j = idx % P;
+    const int64_t ln = tile0 + li;
+    double bh[R];
+    if (ln < a.nlines) {
+      const double *sj = a.scratch + (ln * P + j) * 3 * R;
+      const double *sp = a.scratch + (ln * P + (j + P - 1) % P) * 3 * R;
+      const double *lt = a.LtUt + (size_t)j * 2 * R * R, *ut = lt + R * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double acc = sj[r];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc -= lt[r * R + c] * sp[2 * R + c] + ut[r * R + c] * sj[R + c];
+        bh[r] = acc;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) bh[r] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) xr0[(li * P + j) * R + r] = bh[r];
+  }
+  __syncthreads();
+  double *cur = xr0, *nxt = xr1;
+  for (int ph = 0; ph < a.nphase; ++ph) {
+    const int *ro = a.row_off + ph * (P + 1);
+    for (int idx = p.tid; idx < p.W * P; idx += NT) {
+      const int li = idx / P, j = idx % P;
+      const int t0 = ro[j], t1 = ro[j + 1];
+      double acc[R];
+      if (t0 == t1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = cur[(li * P + j) * R + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int t = t0; t < t1; ++t) {
+          const double *mt = a.mats + (size_t)t * R * R;
+          const double *xs = cur + (li * P + a.src[t]) * R;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[r] += mt[r * R + c] * xs[c];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) nxt[(li * P + j) * R + r] = acc[r];
+    }
+    __syncthreads();
+    double *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  double xi[R], xi1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    xi[r] = cur[(p.li * P + part) * R + r];
+    xi1[r] = cur[(p.li * P + (part + 1) % P) * R + r];
+  }
+  Xchg xc{smem, R, NT, 0, true};
+  double v[M];
+  int start, m;
+  wg_solve_interior<R, M, MODE>(a, p, active, base, part, xc, v, start, m);
+  if (!active) return;
+  const int64_t row0 = a.wg_start[part] + R + start;
+  double *out = a.out + base + row0 * a.rs;
+  const double *sg = a.SR + a.SR_off[part];
+  const int Ni = a.wg_start[part + 1] - a.wg_start[part] - R;
+  const double *rg = sg + (size_t)Ni * R;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    if (k < m) {
+      const int row = start + k;
+      double acc = v[k];
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc -= sg[row * R + c] * xi[c] + rg[row * R + c] * xi1[c];
+      out[k * a.rs] = acc;
+    }
+  }
+  if (p.l == 0) {
+    const int64_t g0 = a.wg_start[part];
+#pragma unroll
+    for (int c = 0; c < R; ++c) a.out[base + (g0 + c) * a.rs] = xi[c];
+  }
+}
+
+// ------------------------------------------------------------------------
+// Standalone periodic stencil b = sum_q c_q f_{j+q} along one axis.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stencil(const StencilArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  // idx enumerates (v, j, u) with u fastest so threads run along x
+  const int64_t u = idx % a.nu;
+  const int64_t rest = idx / a.nu;
+  const int64_t j = rest % a.n;
+  const int64_t vv = rest / a.n;
+  const int64_t base = u * a.su + vv * a.sv;
+  double acc = 0.0;
+  for (int q = a.lo; q <= a.hi; ++q) {
+    int64_t jj = j + q;
+    jj = jj < 0 ? jj + a.n : (jj >= a.n ? jj - a.n : jj);
+    acc += a.c[q - a.lo] * a.f[base + jj * a.rs];
+  }
+  a.b[base + j * a.rs] = acc;
+}
+
+// ------------------------------------------------------------------------
+// Dispatch tables
+// ------------------------------------------------------------------------
+#define CB_LINE_INST(R, M, T, MODE, Q, UNI) \
+  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, (const void *)&k_line<R, M, T, MODE, Q, UNI>}
+
+#define CB_LINE_Q(R, M, T, MODE, UNI) CB_LINE_INST(R, M, T, MODE, 0, UNI), CB_LINE_INST(R, M, T, MODE, 3, UNI)
+#define CB_LINE_MODE(R, M, T, UNI) CB_LINE_Q(R, M, T, MODE_X, UNI), CB_LINE_Q(R, M, T, MODE_S, UNI)
+#define CB_LINE_T(R, M, UNI) CB_LINE_MODE(R, M, double, UNI), CB_LINE_MODE(R, M, float, UNI)
+#define CB_LINE_R(M, UNI) CB_LINE_T(1, M, UNI), CB_LINE_T(2, M, UNI)
+
+static const LineKernel kLineKernels[] = {
+    CB_LINE_R(4, true), CB_LINE_R(6, true), CB_LINE_R(8, true), CB_LINE_R(12, true), CB_LINE_R(16, true),
+    CB_LINE_R(8, false), CB_LINE_R(16, false),
+};
+
+const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni) {
+  for (const auto &k : kLineKernels)
+    if (k.R == R && k.M == M && k.fp32 == fp32 && k.mode == mode && k.Q == Q && k.uni == uni) return k.fn;
+  return nullptr;
+}
+
+#define CB_WG_INST(R, M, MODE) {R, M, MODE, (const void *)&k_wg_a<R, M, MODE>, (const void *)&k_wg_c<R, M, MODE>}
+static const WgKernel kWgKernels[] = {
+    CB_WG_INST(1, 8, MODE_X), CB_WG_INST(1, 8, MODE_S), CB_WG_INST(2, 8, MODE_X), CB_WG_INST(2, 8, MODE_S),
+    CB_WG_INST(1, 16, MODE_X), CB_WG_INST(1, 16, MODE_S), CB_WG_INST(2, 16, MODE_X), CB_WG_INST(2, 16, MODE_S),
+};
+
+const WgKernel *find_wg_kernel(int R, int M, int mode) {
+  for (const auto &k : kWgKernels)
+    if (k.R == R && k.M == M && k.mode == mode) return &k;
+  return nullptr;
+}
+
+const void *stencil_kernel() { return (const void *)&k_stencil; }
+
+}  // namespace cb

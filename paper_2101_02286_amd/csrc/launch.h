@@ -1,0 +1,60 @@
+// Kernel argument blocks and dispatch tables shared by kernels.hip and api.cpp.
+#pragma once
+#include <cstdint>
+
+#include "plan.h"
+
+namespace cb {
+
+// Row layout of a launch: unit-stride lines (MODE_X) or strided lines (MODE_S).
+enum { MODE_X = 0, MODE_S = 1 };
+
+struct LineArgs {
+  const double *in;
+  double *out;
+  int64_t nlines, nu, su, sv, rs;
+  int lgL, lgW, block_sync, refine_iters;
+  SegDev seg;
+  double stc[7];             // stencil coefficients for q = -3..3 (zero padded)
+  double bands[5];           // constant bands a_{-R..R} (refinement residual)
+  const double *bands_row;   // per-row bands [n][2R+1] or nullptr
+};
+
+struct WgArgs {
+  const double *in;
+  double *out;
+  double *scratch;           // [nlines][P][3R]
+  int64_t nlines, nu, su, sv, rs;
+  int lgL, lgW, P, nphase;
+  const SegDev *segs;        // [P]
+  const int *wg_start;       // [P+1]
+  const double *SR;          // S^G, R^G per partition
+  const int64_t *SR_off;     // [P]
+  const double *LtUt;        // [P][2][R][R]
+  const int *row_off, *src;  // reduced program
+  const double *mats;
+};
+
+struct StencilArgs {
+  const double *f;
+  double *b;
+  int64_t total, n, nu, su, sv, rs;
+  int lo, hi;
+  double c[7];
+};
+
+struct LineKernel {
+  int R, M, fp32, mode, Q;
+  bool uni;
+  const void *fn;
+};
+struct WgKernel {
+  int R, M, mode;
+  const void *fn_a, *fn_c;
+};
+
+const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
+const WgKernel *find_wg_kernel(int R, int M, int mode);
+const void *stencil_kernel();
+
+}  // namespace cb

@@ -1,0 +1,730 @@
+// Host-side pre-factorisation of a compact banded matrix (FP64).
+//
+// Everything here is independent of the right-hand side and is computed once
+// per matrix (Sec. 4, the paragraph on pre-factorisation): the generalized
+// PCR multipliers of every interior block (Sec. 2 Eqs. (3)-(6)), the blocks
+// S = D^{-1} L and R = D^{-1} U (Sec. 4 Eqs. (15)-(16)), the reduced blocks
+// of Eqs. (18)-(20), and the multipliers of the block-PCR solve of the
+// reduced system (Sec. 4 Algorithms 1-4).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+namespace cb {
+namespace {
+
+// ------------------------------------------------------------ small dense --
+using Mat = std::vector<double>;  // R x R, row-major
+
+Mat zeros(int R) { return Mat(R * R, 0.0); }
+Mat eye(int R) {
+  Mat m = zeros(R);
+  for (int i = 0; i < R; ++i) m[i * R + i] = 1.0;
+  return m;
+}
+Mat mul(const Mat &a, const Mat &b, int R) {
+  Mat c = zeros(R);
+  for (int i = 0; i < R; ++i)
+    for (int k = 0; k < R; ++k)
+      for (int j = 0; j < R; ++j) c[i * R + j] += a[i * R + k] * b[k * R + j];
+  return c;
+}
+Mat add(const Mat &a, const Mat &b) {
+  Mat c(a);
+  for (size_t i = 0; i < c.size(); ++i) c[i] += b[i];
+  return c;
+}
+Mat sub(const Mat &a, const Mat &b) {
+  Mat c(a);
+  for (size_t i = 0; i < c.size(); ++i) c[i] -= b[i];
+  return c;
+}
+Mat neg(const Mat &a) {
+  Mat c(a);
+  for (auto &v : c) v = -v;
+  return c;
+}
+
+// Gauss-Jordan inverse with partial pivoting; false when numerically singular
+// (pivot below 1e-12 of the largest entry).
+bool inverse(const Mat &a, int R, Mat &out) {
+  Mat m(a);
+  out = eye(R);
+  double amax = 0.0;
+  for (double v : m) amax = std::max(amax, std::fabs(v));
+  if (!(amax > 0.0) || !std::isfinite(amax)) return false;
+  for (int k = 0; k < R; ++k) {
+    int p = k;
+    for (int i = k + 1; i < R; ++i)
+      if (std::fabs(m[i * R + k]) > std::fabs(m[p * R + k])) p = i;
+    if (!(std::fabs(m[p * R + k]) > 1e-12 * amax)) return false;
+    if (p != k)
+      for (int j = 0; j < R; ++j) {
+        std::swap(m[k * R + j], m[p * R + j]);
+        std::swap(out[k * R + j], out[p * R + j]);
+      }
+    const double d = 1.0 / m[k * R + k];
+    for (int j = 0; j < R; ++j) {
+      m[k * R + j] *= d;
+      out[k * R + j] *= d;
+    }
+    for (int i = 0; i < R; ++i) {
+      if (i == k) continue;
+      const double f = m[i * R + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < R; ++j) {
+        m[i * R + j] -= f * m[k * R + j];
+        out[i * R + j] -= f * out[k * R + j];
+      }
+    }
+  }
+  return true;
+}
+
+// Small dense solve (size <= 4), partial pivoting.
+bool small_solve(int m, double *a, double *x, double scale) {
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::fabs(a[i * m + k]) > std::fabs(a[p * m + k])) p = i;
+    if (!(std::fabs(a[p * m + k]) > 1e-13 * scale)) return false;
+    if (p != k) {
+      for (int j = 0; j < m; ++j) std::swap(a[k * m + j], a[p * m + j]);
+      std::swap(x[k], x[p]);
+    }
+    for (int i = k + 1; i < m; ++i) {
+      const double l = a[i * m + k] / a[k * m + k];
+      for (int j = k; j < m; ++j) a[i * m + j] -= l * a[k * m + j];
+      x[i] -= l * x[k];
+    }
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int j = i + 1; j < m; ++j) s -= a[i * m + j] * x[j];
+    x[i] = s / a[i * m + i];
+  }
+  return true;
+}
+
+int ceil_log2(int v) {
+  int t = 0;
+  while ((1 << t) < v) ++t;
+  return t;
+}
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ------------------------------------------------- generalized PCR (Sec. 2) --
+// An acyclic banded block D of N rows: band[j*(2R+1) + o+R] = D[j][j+o].
+struct GPCR {
+  int N = 0, R = 0, T = 0;
+  std::vector<double> k;     // [T][N][2R]
+  std::vector<double> dinv;  // [N]
+};
+
+inline int kidx(int q, int R) { return q < 0 ? R + q : R + q - 1; }
+
+// Factor D by generalized PCR (Eq. (3)): at level t (stride s = 2^t) row j
+// becomes a_j - sum_q k_q a_{j+qs}, with the k_q chosen so the entries at odd
+// multiples of s vanish (Eq. (4); tridiagonal Eq. (5), pentadiagonal Eq. (6)).
+// Near the ends of D the neighbour rows j+qs outside D are absent and so are
+// the equations of columns outside D; when a side has more rows than
+// equations the outermost rows of that side get k = 0 (the equation they
+// would serve is vacuous).  `T` levels are stored (>= ceil(log2 N); extra
+// levels have k = 0).
+cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR &g,
+                      std::string &msg) {
+  const int W = 2 * R + 1;
+  g.N = N;
+  g.R = R;
+  g.T = T;
+  g.k.assign((size_t)T * N * 2 * R, 0.0);
+  g.dinv.assign(N, 0.0);
+  std::vector<double> c(band), cn(band.size());
+  double scale = 0.0;
+  for (double v : band) scale = std::max(scale, std::fabs(v));
+  // D_cur[j][j + o*s] = c[j*W + o+R]
+  auto at = [&](int row, int o) -> double {  // entry of row at offset o*s
+    if (o < -R || o > R) return 0.0;
+    return c[row * W + o + R];
+  };
+  for (int t = 0; t < T; ++t) {
+    const int s = 1 << t;
+    for (int j = 0; j < N; ++j) {
+      const int Qm = std::min(2 * R, j / s);            // rows above at stride s
+      const int Qp = std::min(2 * R, (N - 1 - j) / s);  // rows below
+      const int Em = (std::min(2 * R - 1, Qm) + 1) / 2;  // equations/unknowns above
+      const int Ep = (std::min(2 * R - 1, Qp) + 1) / 2;
+      int qs[4], os[4];
+      int m = 0;
+      for (int q = Em; q >= 1; --q) qs[m++] = -q;
+      for (int q = 1; q <= Ep; ++q) qs[m++] = q;
+      int e = 0;
+      for (int q = Em; q >= 1; --q) os[e++] = -(2 * q - 1);
+      for (int q = 1; q <= Ep; ++q) os[e++] = 2 * q - 1;
+      double a[16], x[4];
+      for (int r = 0; r < m; ++r) {
+        x[r] = at(j, os[r]);
+        for (int u = 0; u < m; ++u) a[r * m + u] = at(j + qs[u] * s, os[r] - qs[u]);
+      }
+      if (m > 0 && !small_solve(m, a, x, scale)) {
+        msg = "generalized PCR reduction system is singular";
+        return CB_ERR_SINGULAR;
+      }
+      for (int u = 0; u < m; ++u) g.k[((size_t)t * N + j) * 2 * R + kidx(qs[u], R)] = x[u];
+      // the new row keeps the even multiples of s: offsets 2*o2*s, o2 in [-R, R]
+      for (int o2 = -R; o2 <= R; ++o2) {
+        double v = at(j, 2 * o2);
+        for (int u = 0; u < m; ++u) v -= x[u] * at(j + qs[u] * s, 2 * o2 - qs[u]);
+        // offsets that leave D are structurally zero
+        const int col = j + 2 * o2 * s;
+        cn[j * W + o2 + R] = (col >= 0 && col < N) ? v : 0.0;
+      }
+    }
+    std::swap(c, cn);
+  }
+  for (int j = 0; j < N; ++j) {
+    for (int o = -R; o <= R; ++o)
+      if (o != 0 && c[j * W + o + R] != 0.0) {
+        msg = "internal: generalized PCR did not reach a diagonal system";
+        return CB_ERR_INVALID_ARG;
+      }
+    const double d = c[j * W + R];
+    if (!(std::fabs(d) > 1e-13 * scale)) {
+      msg = "generalized PCR produced a zero pivot (singular block)";
+      return CB_ERR_SINGULAR;
+    }
+    g.dinv[j] = 1.0 / d;
+  }
+  return CB_OK;
+}
+
+// y = D^{-1} rhs for one column (length N), by the stored levels.
+void gpcr_apply(const GPCR &g, double *y) {
+  const int N = g.N, R = g.R;
+  std::vector<double> yn(N);
+  for (int t = 0; t < g.T; ++t) {
+    const int s = 1 << t;
+    for (int j = 0; j < N; ++j) {
+      double v = y[j];
+      for (int q = 1; q <= R; ++q) {
+        if (j - q * s >= 0) v -= g.k[((size_t)t * N + j) * 2 * R + kidx(-q, R)] * y[j - q * s];
+        if (j + q * s < N) v -= g.k[((size_t)t * N + j) * 2 * R + kidx(q, R)] * y[j + q * s];
+      }
+      yn[j] = v;
+    }
+    std::copy(yn.begin(), yn.end(), y);
+  }
+  for (int j = 0; j < N; ++j) y[j] *= g.dinv[j];
+}
+
+// ------------------------------------------------ partitioned blocks (Sec. 3) --
+// A run of S rows split into P parts; part i has rows [st[i], st[i+1]), its
+// first R rows are interface rows and the rest the interior block D_i.
+// coef(g, o) returns A[row g][row g + o] of the run.  When `cyclic`, part
+// indices wrap modulo P; otherwise couplings leaving the run are dropped.
+struct Blocks {
+  int P, R;
+  std::vector<int> st;
+  std::vector<GPCR> D;
+  std::vector<std::vector<double>> Sm, Rm;  // per part: [N_i][R]
+  std::vector<Mat> Dt, Lt, Ut;               // per part R x R
+  std::vector<Mat> Lh, Dh, Uh;               // reduced blocks, Eqs. (18)-(20)
+};
+
+cb_status build_blocks(int P, int R, const std::vector<int> &st, bool cyclic,
+                       const std::function<double(int, int)> &coef, int Tfix, Blocks &B,
+                       std::string &msg) {
+  const int W = 2 * R + 1;
+  B.P = P;
+  B.R = R;
+  B.st = st;
+  B.D.resize(P);
+  B.Sm.resize(P);
+  B.Rm.resize(P);
+  B.Dt.assign(P, zeros(R));
+  B.Lt.assign(P, zeros(R));
+  B.Ut.assign(P, zeros(R));
+  for (int i = 0; i < P; ++i) {
+    const int s0 = st[i], m = st[i + 1] - st[i], N = m - R;
+    if (N < R) {
+      msg = "a partition has fewer than 2r rows";
+      return CB_ERR_INVALID_ARG;
+    }
+    std::vector<double> band((size_t)N * W, 0.0), Lc((size_t)N * R, 0.0), Uc((size_t)N * R, 0.0);
+    for (int j = 0; j < N; ++j)
+      for (int o = -R; o <= R; ++o) {
+        const int t = j + o;
+        const double v = coef(s0 + R + j, o);
+        if (t < 0) {
+          Lc[j * R + (R + t)] = v;  // interface row R+t of this part
+        } else if (t < N) {
+          band[j * W + o + R] = v;
+        } else {  // interface row t-N of the next part
+          if (!cyclic && i == P - 1) continue;
+          Uc[j * R + (t - N)] = v;
+        }
+      }
+    for (int a = 0; a < R; ++a)
+      for (int o = -R; o <= R; ++o) {
+        const int t = a + o;
+        const double v = coef(s0 + a, o);
+        if (t < 0) {
+          if (!cyclic && i == 0) continue;
+          B.Lt[i][a * R + (R + t)] = v;  // last R interior rows of part i-1
+        } else if (t < R) {
+          B.Dt[i][a * R + t] = v;
+        } else {
+          B.Ut[i][a * R + (t - R)] = v;  // first R interior rows of part i
+        }
+      }
+    const int T = Tfix >= 0 ? Tfix : ceil_log2(N);
+    cb_status stt = gpcr_factor(N, R, band, T, B.D[i], msg);
+    if (stt != CB_OK) return stt;
+    // S_i = D_i^{-1} L_i, R_i = D_i^{-1} U_i (Eqs. (15)-(16)), column by column
+    B.Sm[i].assign((size_t)N * R, 0.0);
+    B.Rm[i].assign((size_t)N * R, 0.0);
+    std::vector<double> col(N);
+    for (int c = 0; c < R; ++c) {
+      for (int j = 0; j < N; ++j) col[j] = Lc[j * R + c];
+      gpcr_apply(B.D[i], col.data());
+      for (int j = 0; j < N; ++j) B.Sm[i][j * R + c] = col[j];
+      for (int j = 0; j < N; ++j) col[j] = Uc[j * R + c];
+      gpcr_apply(B.D[i], col.data());
+      for (int j = 0; j < N; ++j) B.Rm[i][j * R + c] = col[j];
+    }
+  }
+  // Eqs. (18)-(20): only the last R rows of S_{i-1}, R_{i-1} and the first R
+  // rows of S_i, R_i enter (the sparsity of L~ and U~).
+  B.Lh.assign(P, zeros(R));
+  B.Dh.assign(P, zeros(R));
+  B.Uh.assign(P, zeros(R));
+  for (int i = 0; i < P; ++i) {
+    const int ip = (i + P - 1) % P;
+    const int Np = st[ip + 1] - st[ip] - R;
+    Mat Sl = zeros(R), Rl = zeros(R), Sf = zeros(R), Rf = zeros(R);
+    for (int a = 0; a < R; ++a)
+      for (int c = 0; c < R; ++c) {
+        Sl[a * R + c] = B.Sm[ip][(Np - R + a) * R + c];
+        Rl[a * R + c] = B.Rm[ip][(Np - R + a) * R + c];
+        Sf[a * R + c] = B.Sm[i][a * R + c];
+        Rf[a * R + c] = B.Rm[i][a * R + c];
+      }
+    B.Lh[i] = neg(mul(B.Lt[i], Sl, R));
+    B.Dh[i] = sub(sub(B.Dt[i], mul(B.Lt[i], Rl, R)), mul(B.Ut[i], Sf, R));
+    B.Uh[i] = neg(mul(B.Ut[i], Rf, R));
+  }
+  return CB_OK;
+}
+
+// --------------------------------------------- reduced block PCR (Alg. 3) --
+// Power-of-two P: log2(P) block-PCR levels, then the final solve with the
+// couplings that alias the row itself folded into the diagonal block.
+cb_status lane_block_pcr(const Blocks &B, std::vector<double> &red, std::vector<double> &wf,
+                         std::string &msg) {
+  const int P = B.P, R = B.R, RR = R * R;
+  std::vector<Mat> W(B.Dh), Lh(B.Lh), Uh(B.Uh);
+  const int T = ceil_log2(P);
+  red.assign((size_t)T * P * 2 * RR, 0.0);
+  for (int t = 0; t < T; ++t) {
+    const int s = 1 << t;
+    std::vector<Mat> Winv(P);
+    for (int i = 0; i < P; ++i)
+      if (!inverse(W[i], R, Winv[i])) {
+        msg = "reduced system: singular diagonal block during block PCR";
+        return CB_ERR_SINGULAR;
+      }
+    std::vector<Mat> W2(P), L2(P), U2(P);
+    for (int i = 0; i < P; ++i) {
+      const int ip = (i + s) % P, im = (i - s % P + P) % P;
+      Mat MU = mul(Uh[i], Winv[ip], R), ML = mul(Lh[i], Winv[im], R);
+      W2[i] = sub(sub(W[i], mul(MU, Lh[ip], R)), mul(ML, Uh[im], R));
+      L2[i] = neg(mul(ML, Lh[im], R));
+      U2[i] = neg(mul(MU, Uh[ip], R));
+      std::copy(MU.begin(), MU.end(), red.begin() + (((size_t)t * P + i) * 2 + 0) * RR);
+      std::copy(ML.begin(), ML.end(), red.begin() + (((size_t)t * P + i) * 2 + 1) * RR);
+    }
+    W.swap(W2);
+    Lh.swap(L2);
+    Uh.swap(U2);
+  }
+  wf.assign((size_t)P * RR, 0.0);
+  for (int i = 0; i < P; ++i) {
+    Mat inv;
+    if (!inverse(add(add(W[i], Lh[i]), Uh[i]), R, inv)) {
+      msg = "reduced system is singular (the matrix A is singular)";
+      return CB_ERR_SINGULAR;
+    }
+    std::copy(inv.begin(), inv.end(), wf.begin() + (size_t)i * RR);
+  }
+  return CB_OK;
+}
+
+// Algorithm 1's level loop for any P (Algorithms 2-4), written as phases.
+cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
+  const int P = B.P, R = B.R, RR = R * R;
+  pg.P = P;
+  pg.R = R;
+  std::vector<Mat> W(B.Dh), Lh(B.Lh), Uh(B.Uh);
+  struct Term { int dst, src; Mat m; };
+  std::vector<std::vector<Term>> phases;
+  auto emit = [&](std::vector<Term> &&terms) { phases.push_back(std::move(terms)); };
+  auto inv_of = [&](const Mat &a, Mat &out) -> bool {
+    if (!inverse(a, R, out)) {
+      msg = "reduced system: singular diagonal block";
+      return false;
+    }
+    return true;
+  };
+  int s = 1, n0 = P, na = P;
+  std::vector<int> stack;
+  struct Det { int d; Mat Winv, Lh, Uh; };
+  std::vector<std::vector<Det>> det_levels;
+  while (n0 > 1) {
+    const int odd = n0 % 2;
+    stack.push_back(odd);
+    if (odd) {
+      n0 -= 1;
+      na -= s;
+      // Algorithm 2: the last row d of each sub-system eliminates its
+      // couplings into its predecessor d-s and into the sub-system's first
+      // row d-na (its cyclic successor), then leaves.
+      std::vector<Term> terms;
+      std::vector<Det> dets;
+      std::vector<Mat> W2(W), L2(Lh), U2(Uh);
+      std::vector<int> rows;
+      for (int d = na; d < na + s; ++d) {
+        Mat Wd;
+        if (!inv_of(W[d], Wd)) return CB_ERR_SINGULAR;
+        const int i1 = d - s, i2 = d - na;
+        Mat M1 = mul(Uh[i1], Wd, R), M2 = mul(Lh[i2], Wd, R);
+        W2[i1] = sub(W2[i1], mul(M1, Lh[d], R));
+        U2[i1] = neg(mul(M1, Uh[d], R));
+        W2[i2] = sub(W2[i2], mul(M2, Uh[d], R));
+        L2[i2] = neg(mul(M2, Lh[d], R));
+        terms.push_back({i1, i1, eye(R)});
+        terms.push_back({i1, d, neg(M1)});
+        terms.push_back({i2, i2, eye(R)});
+        terms.push_back({i2, d, neg(M2)});
+        dets.push_back({d, Wd, Lh[d], Uh[d]});
+        rows.push_back(d);
+      }
+      W.swap(W2);
+      Lh.swap(L2);
+      Uh.swap(U2);
+      emit(std::move(terms));
+      det_levels.push_back(std::move(dets));
+      pg.detached.push_back(rows);
+      pg.detach_steps++;
+    } else {
+      det_levels.emplace_back();
+      pg.detached.emplace_back();
+    }
+    // Algorithm 3 on the attached rows, neighbours modulo na.
+    std::vector<Mat> Winv(na);
+    for (int i = 0; i < na; ++i)
+      if (!inv_of(W[i], Winv[i])) return CB_ERR_SINGULAR;
+    std::vector<Term> terms;
+    std::vector<Mat> W2(W), L2(Lh), U2(Uh);
+    for (int i = 0; i < na; ++i) {
+      const int ip = (i + s) % na, im = (i - s % na + na) % na;
+      Mat MU = mul(Uh[i], Winv[ip], R), ML = mul(Lh[i], Winv[im], R);
+      W2[i] = sub(sub(W[i], mul(MU, Lh[ip], R)), mul(ML, Uh[im], R));
+      L2[i] = neg(mul(ML, Lh[im], R));
+      U2[i] = neg(mul(MU, Uh[ip], R));
+      terms.push_back({i, i, eye(R)});
+      terms.push_back({i, ip, neg(MU)});
+      terms.push_back({i, im, neg(ML)});
+    }
+    W.swap(W2);
+    Lh.swap(L2);
+    Uh.swap(U2);
+    emit(std::move(terms));
+    pg.pcr_steps++;
+    s *= 2;
+    n0 /= 2;
+  }
+  // Final solve of the attached rows: the couplings at +-s alias the row.
+  {
+    std::vector<Term> terms;
+    for (int i = 0; i < na; ++i) {
+      Mat inv;
+      if (!inverse(add(add(W[i], Lh[i]), Uh[i]), R, inv)) {
+        msg = "reduced system is singular (the matrix A is singular)";
+        return CB_ERR_SINGULAR;
+      }
+      terms.push_back({i, i, inv});
+    }
+    emit(std::move(terms));
+  }
+  // Algorithm 4, in reverse level order: x_d = W_d^{-1}(x_d - L^_d x_{d-s} - U^_d x_{d-na}).
+  while (!stack.empty()) {
+    n0 *= 2;
+    s /= 2;
+    const int odd = stack.back();
+    stack.pop_back();
+    std::vector<Det> dets = std::move(det_levels.back());
+    det_levels.pop_back();
+    if (odd) {
+      std::vector<Term> terms;
+      for (const Det &dt : dets) {
+        const int d = dt.d;
+        terms.push_back({d, d, dt.Winv});
+        terms.push_back({d, d - s, neg(mul(dt.Winv, dt.Lh, R))});
+        terms.push_back({d, d - na, neg(mul(dt.Winv, dt.Uh, R))});
+      }
+      emit(std::move(terms));
+      na += s;
+      n0 += 1;
+    }
+  }
+  // Flatten: terms sorted by (phase, dst).
+  pg.nphase = (int)phases.size();
+  pg.row_off.assign((size_t)pg.nphase * (P + 1), 0);
+  pg.src.clear();
+  pg.mats.clear();
+  for (int ph = 0; ph < pg.nphase; ++ph) {
+    auto &terms = phases[ph];
+    std::stable_sort(terms.begin(), terms.end(),
+                     [](const Term &a, const Term &b) { return a.dst < b.dst; });
+    size_t pos = 0;
+    for (int dst = 0; dst <= P; ++dst) {
+      pg.row_off[(size_t)ph * (P + 1) + dst] = (int)pg.src.size();
+      while (dst < P && pos < terms.size() && terms[pos].dst == dst) {
+        pg.src.push_back(terms[pos].src);
+        pg.mats.insert(pg.mats.end(), terms[pos].m.begin(), terms[pos].m.end());
+        ++pos;
+      }
+    }
+  }
+  (void)RR;
+  return CB_OK;
+}
+
+// ---------------------------------------------------- segment (lane level) --
+bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
+                 bool allow_uniform, int L_req = 0) {
+  static const int kUniM[] = {8, 16, 12, 6, 4};
+  if (allow_uniform) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int m : kUniM) {
+        if (M_req && m != M_req) continue;
+        if (m < 2 * R || S % m) continue;
+        const int l = S / m;
+        if (!is_pow2(l) || l > (pass == 0 ? 64 : 1024)) continue;
+        L = l;
+        M = m;
+        uniform = true;
+        m_uni = m;
+        return true;
+      }
+  }
+  uniform = false;
+  m_uni = 0;
+  M = M_req ? M_req : ((S + 7) / 8 <= 64 ? 8 : 16);
+  if (M != 8 && M != 16) return false;
+  if (L_req > 0) {
+    L = L_req;
+  } else {
+    L = 1;
+    while (L * M < S) L *= 2;
+    while (L > 1 && S / L < 2 * R) L /= 2;
+  }
+  if (L > 1024 || (S + L - 1) / L > M || S / L < 2 * R) return false;
+  return true;
+}
+
+cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
+                        const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
+                        std::string &msg, int L_req = 0) {
+  int L, M, m_uni;
+  bool uni;
+  if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req)) {
+    msg = "no lane layout for this segment length (rows_per_lane unsupported?)";
+    return CB_ERR_UNSUPPORTED;
+  }
+  sp.S = S;
+  sp.cyclic = cyclic;
+  sp.L = L;
+  sp.M = M;
+  sp.R = R;
+  sp.N = M - R;
+  sp.Tint = ceil_log2(sp.N);
+  sp.Tred = ceil_log2(L);
+  sp.uniform = uni;
+  sp.m_uniform = m_uni;
+  std::vector<int> st(L + 1);
+  const int base = S / L, extra = S % L;
+  st[0] = 0;
+  for (int l = 0; l < L; ++l) st[l + 1] = st[l] + base + (l < extra ? 1 : 0);
+  sp.lane_start = st;
+  Blocks B;
+  cb_status s = build_blocks(L, R, st, cyclic, coef, sp.Tint, B, msg);
+  if (s != CB_OK) return s;
+  // coefficient blocks, padded to N = M-R slots, deduplicated by content
+  const int blk = coef_block_size(R, M, sp.Tint);
+  const CoefOff off = coef_offsets(R, M, sp.Tint);
+  sp.block = blk;
+  sp.lane_type.assign(L, 0);
+  sp.coef.clear();
+  sp.ntypes = 0;
+  const int N = sp.N;
+  for (int l = 0; l < L; ++l) {
+    std::vector<double> b(blk, 0.0);
+    const int Nl = st[l + 1] - st[l] - R;
+    for (int t = 0; t < sp.Tint; ++t)
+      for (int j = 0; j < Nl; ++j)
+        for (int u = 0; u < 2 * R; ++u)
+          b[off.k + ((size_t)t * N + j) * 2 * R + u] = B.D[l].k[((size_t)t * Nl + j) * 2 * R + u];
+    for (int j = 0; j < Nl; ++j) b[off.dinv + j] = B.D[l].dinv[j];
+    for (int q = 0; q < R * R; ++q) {
+      b[off.Lt + q] = B.Lt[l][q];
+      b[off.Ut + q] = B.Ut[l][q];
+    }
+    for (int j = 0; j < Nl; ++j)
+      for (int c = 0; c < R; ++c) {
+        b[off.S + j * R + c] = B.Sm[l][j * R + c];
+        b[off.Rm + j * R + c] = B.Rm[l][j * R + c];
+      }
+    int found = -1;
+    for (int ty = 0; ty < sp.ntypes; ++ty)
+      if (std::memcmp(&sp.coef[(size_t)ty * blk], b.data(), sizeof(double) * blk) == 0) {
+        found = ty;
+        break;
+      }
+    if (found < 0) {
+      found = sp.ntypes++;
+      sp.coef.insert(sp.coef.end(), b.begin(), b.end());
+    }
+    sp.lane_type[l] = found;
+  }
+  if (uni && sp.ntypes != 1) {
+    msg = "internal: uniform layout produced differing lane partitions";
+    return CB_ERR_INVALID_ARG;
+  }
+  return lane_block_pcr(B, sp.red, sp.wf, msg);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plan --
+cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
+  if (d.r < 1 || d.r > 2) {
+    msg = "r must be 1 (tridiagonal) or 2 (pentadiagonal)";
+    return d.r > 2 ? CB_ERR_UNSUPPORTED : CB_ERR_INVALID_ARG;
+  }
+  if (!d.bands) {
+    msg = "bands is NULL";
+    return CB_ERR_INVALID_ARG;
+  }
+  if (d.precision < CB_FP64 || d.precision > CB_FP32_REFINE) {
+    msg = "unknown precision";
+    return CB_ERR_INVALID_ARG;
+  }
+  if (d.rows_per_lane && d.rows_per_lane != 4 && d.rows_per_lane != 6 && d.rows_per_lane != 8 &&
+      d.rows_per_lane != 12 && d.rows_per_lane != 16) {
+    msg = "rows_per_lane must be 0, 4, 6, 8, 12 or 16";
+    return CB_ERR_UNSUPPORTED;
+  }
+  const int R = d.r, n = d.n, W = 2 * R + 1;
+  const int P = d.partitions <= 0 ? 1 : d.partitions;
+  if (P > 64) {
+    msg = "at most 64 workgroup partitions per line";
+    return CB_ERR_UNSUPPORTED;
+  }
+  if (n < 2 * R * P + (P == 1 ? 0 : R * P) || n < 2 * R + 1 || n > (1 << 24)) {
+    msg = "line length n too small for r and the partition count (or too large)";
+    return CB_ERR_INVALID_ARG;
+  }
+  p.desc = d;
+  p.desc.bands = nullptr;
+  p.R = R;
+  p.n = n;
+  p.P = P;
+  p.precision = d.precision;
+  p.refine_iters = d.precision == CB_FP32_REFINE ? (d.refine_iters > 0 ? d.refine_iters : 2) : 0;
+  if (p.refine_iters > 8) {
+    msg = "at most 8 refinement iterations";
+    return CB_ERR_INVALID_ARG;
+  }
+  p.bands.assign((size_t)n * W, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int o = 0; o < W; ++o) {
+      const double v = d.per_row ? d.bands[(size_t)j * W + o] : d.bands[o];
+      if (!std::isfinite(v)) {
+        msg = "bands contain a non-finite value";
+        return CB_ERR_INVALID_ARG;
+      }
+      p.bands[(size_t)j * W + o] = v;
+    }
+  if (!d.cyclic) {  // acyclic: entries outside the matrix are ignored
+    for (int j = 0; j < n; ++j)
+      for (int o = -R; o <= R; ++o)
+        if (j + o < 0 || j + o >= n) p.bands[(size_t)j * W + o + R] = 0.0;
+  }
+  const bool per_row = d.per_row != 0;
+  const bool cyclic = d.cyclic != 0;
+  auto line_coef = [&](int g, int o) -> double { return p.bands[(size_t)g * W + o + R]; };
+
+  if (P == 1) {
+    p.segs.resize(1);
+    cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg);
+    if (s != CB_OK) return s;
+    p.M = p.segs[0].M;
+    p.L = p.segs[0].L;
+    p.wg_start = {0, n};
+    return CB_OK;
+  }
+  // P > 1: workgroup partitions, each with R interface rows and an interior
+  // segment D_i solved by the lane-level scheme.
+  p.wg_start.assign(P + 1, 0);
+  const int base = n / P, extra = n % P;
+  for (int i = 0; i < P; ++i) p.wg_start[i + 1] = p.wg_start[i] + base + (i < extra ? 1 : 0);
+  Blocks B;
+  cb_status s = build_blocks(P, R, p.wg_start, cyclic, line_coef, -1, B, msg);
+  if (s != CB_OK) return s;
+  // one lane layout for all partitions (the kernel has one M)
+  int M = d.rows_per_lane, Lg = 0;
+  {
+    const int Smax = base + (extra ? 1 : 0) - R;
+    int m_uni;
+    bool uni;
+    if (!lane_layout(Smax, R, M, Lg, M, uni, m_uni, false)) {
+      msg = "no lane layout for the partition size";
+      return CB_ERR_UNSUPPORTED;
+    }
+  }
+  p.segs.resize(P);
+  for (int i = 0; i < P; ++i) {
+    const int g0 = p.wg_start[i] + R;
+    const int S = p.wg_start[i + 1] - g0;
+    auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
+    s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg);
+    if (s != CB_OK) return s;
+  }
+  p.M = M;
+  p.L = p.segs[0].L;
+  for (int i = 1; i < P; ++i)
+    if (p.segs[i].L != p.L) {
+      msg = "partition sizes need different lane counts; choose n divisible by P";
+      return CB_ERR_UNSUPPORTED;
+    }
+  p.SRg.clear();
+  p.SRg_off.assign(P, 0);
+  for (int i = 0; i < P; ++i) {
+    p.SRg_off[i] = (int64_t)p.SRg.size();
+    p.SRg.insert(p.SRg.end(), B.Sm[i].begin(), B.Sm[i].end());
+    p.SRg.insert(p.SRg.end(), B.Rm[i].begin(), B.Rm[i].end());
+  }
+  p.LtUtg.assign((size_t)P * 2 * R * R, 0.0);
+  for (int i = 0; i < P; ++i)
+    for (int q = 0; q < R * R; ++q) {
+      p.LtUtg[((size_t)i * 2 + 0) * R * R + q] = B.Lt[i][q];
+      p.LtUtg[((size_t)i * 2 + 1) * R * R + q] = B.Ut[i][q];
+    }
+  return wg_program(B, p.prog, msg);
+}
+
+}  // namespace cb

@@ -1,0 +1,133 @@
+"""NumPy re-enactment of the kernels' arithmetic on a host-only plan's arrays.
+
+Test helper only: it lets the CPU suite check the host factorisation (plan)
+end to end against the oracle without a GPU.  It follows the same steps as
+the device code -- interior generalized PCR per lane, interface RHS, block
+PCR across lanes, back-substitution, and for P > 1 the workgroup-level
+program -- but shares no code with it.
+"""
+import numpy as np
+
+
+def _offsets(R, M, T):
+    N = M - R
+    k = 0
+    dinv = T * N * 2 * R
+    Lt = dinv + N
+    Ut = Lt + R * R
+    S = Ut + R * R
+    Rm = S + N * R
+    return dict(k=k, dinv=dinv, Lt=Lt, Ut=Ut, S=S, Rm=Rm, end=Rm + N * R)
+
+
+def solve_segment(plan, b, seg=0):
+    """b: (lines, S) -> x = D_seg^{-1} b by the lane scheme (cyclic or acyclic per plan)."""
+    info = plan.info()
+    R, M, L = info["r"], info["rows_per_lane"], info["lanes"]
+    N = M - R
+    types = plan.array(3, seg).astype(int)
+    starts = plan.array(4, seg).astype(int)
+    L = len(types)
+    T = 0
+    while (1 << T) < N:
+        T += 1
+    o = _offsets(R, M, T)
+    coef = plan.array(0, seg).reshape(-1, o["end"])
+    Tred = 0
+    while (1 << Tred) < L:
+        Tred += 1
+    red = plan.array(1, seg).reshape(Tred, L, 2, R, R)
+    wf = plan.array(2, seg).reshape(L, R, R)
+    nl = b.shape[0]
+    v = np.zeros((L, nl, M))
+    m = np.diff(starts)
+    for l in range(L):
+        v[l, :, :m[l]] = b[:, starts[l]:starts[l + 1]]
+    # interior generalized PCR
+    y = v[:, :, R:].copy()
+    for t in range(T):
+        s = 1 << t
+        yn = y.copy()
+        for l in range(L):
+            k = coef[types[l], o["k"]:o["dinv"]].reshape(T, N, 2 * R)
+            for j in range(N):
+                for q in range(1, R + 1):
+                    if j - q * s >= 0:
+                        yn[l, :, j] -= k[t, j, R - q] * y[l, :, j - q * s]
+                    if j + q * s < N:
+                        yn[l, :, j] -= k[t, j, R + q - 1] * y[l, :, j + q * s]
+        y = yn
+    for l in range(L):
+        y[l] *= coef[types[l], o["dinv"]:o["Lt"]][None, :]
+    # interface RHS
+    xt = np.zeros((L, nl, R))
+    for l in range(L):
+        lp = (l - 1) % L
+        nlp = m[lp] - R
+        yprev = y[lp, :, nlp - R:nlp]
+        Lt = coef[types[l], o["Lt"]:o["Ut"]].reshape(R, R)
+        Ut = coef[types[l], o["Ut"]:o["S"]].reshape(R, R)
+        xt[l] = v[l, :, :R] - yprev @ Lt.T - y[l, :, :R] @ Ut.T
+    # block PCR across lanes
+    for t in range(Tred):
+        s = 1 << t
+        xn = xt.copy()
+        for l in range(L):
+            xn[l] -= xt[(l + s) % L] @ red[t, l, 0].T + xt[(l - s) % L] @ red[t, l, 1].T
+        xt = xn
+    for l in range(L):
+        xt[l] = xt[l] @ wf[l].T
+    # back-substitution
+    x = np.zeros_like(b)
+    for l in range(L):
+        S = coef[types[l], o["S"]:o["Rm"]].reshape(N, R)
+        Rm = coef[types[l], o["Rm"]:o["end"]].reshape(N, R)
+        xl = y[l] - xt[l] @ S.T - xt[(l + 1) % L] @ Rm.T
+        x[:, starts[l]:starts[l] + R] = xt[l]
+        x[:, starts[l] + R:starts[l + 1]] = xl[:, :m[l] - R]
+    return x
+
+
+def solve(plan, b):
+    """x = A^{-1} b for (lines, n) b, following the plan's decomposition."""
+    info = plan.info()
+    P, R = info["partitions"], info["r"]
+    if P == 1:
+        return solve_segment(plan, b, 0)
+    ws = plan.array(7).astype(int)
+    SR = plan.array(5)
+    LtUt = plan.array(6).reshape(P, 2, R, R)
+    nl = b.shape[0]
+    ys, sr = [], []
+    off = 0
+    for i in range(P):
+        seg = b[:, ws[i] + R:ws[i + 1]]
+        ys.append(solve_segment(plan, seg, i))
+        Ni = ws[i + 1] - ws[i] - R
+        sr.append((SR[off:off + Ni * R].reshape(Ni, R), SR[off + Ni * R:off + 2 * Ni * R].reshape(Ni, R)))
+        off += 2 * Ni * R
+    xr = np.zeros((P, nl, R))
+    for i in range(P):
+        ip = (i - 1) % P
+        xr[i] = b[:, ws[i]:ws[i] + R] - ys[ip][:, -R:] @ LtUt[i, 0].T - ys[i][:, :R] @ LtUt[i, 1].T
+    row_off = plan.array(8).astype(int)
+    src = plan.array(9).astype(int)
+    mats = plan.array(10).reshape(-1, R, R)
+    nph = len(row_off) // (P + 1)
+    for ph in range(nph):
+        ro = row_off[ph * (P + 1):(ph + 1) * (P + 1)]
+        xn = xr.copy()
+        for j in range(P):
+            if ro[j] == ro[j + 1]:
+                continue
+            acc = np.zeros((nl, R))
+            for t in range(ro[j], ro[j + 1]):
+                acc += xr[src[t]] @ mats[t].T
+            xn[j] = acc
+        xr = xn
+    x = np.zeros_like(b)
+    for i in range(P):
+        Sg, Rg = sr[i]
+        x[:, ws[i]:ws[i] + R] = xr[i]
+        x[:, ws[i] + R:ws[i + 1]] = ys[i] - xr[i] @ Sg.T - xr[(i + 1) % P] @ Rg.T
+    return x

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 and FP32+refinement results must match the oracle to a
+relative max error of 1e-12 (max |x - x_ref| / max |x_ref|); plain FP32 to
+1e-6 for tridiagonal systems (measured and reported for pentadiagonal).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import schemes
+from paper_2101_02286_amd import cb, synth
+
+pytestmark = pytest.mark.gpu
+
+TRI = schemes.bands_collocated(schemes.DERIV6)
+PENTA = schemes.bands_collocated(schemes.DERIV10)
+INTERP = [float(schemes.INTERP6["alpha"]), 1.0, float(schemes.INTERP6["alpha"])]
+
+
+def relerr(x, ref):
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def deriv_stencil(scheme, n):
+    lo, c = schemes.stencil_deriv_collocated(scheme, 2 * math.pi / n)
+    return lo, c
+
+
+def shape_with(axis, n, other=(12, 20)):
+    dims = [other[0], other[1]]
+    dims.insert(axis, n)  # dims in (x, y, z) order
+    return (dims[2], dims[1], dims[0])
+
+
+# ---------------------------------------------------------- fused derivative
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_c1_32cubed_derivative(gpu, axis):
+    shape = (32, 32, 32)
+    f, modes = synth.random_modes(shape, seed=0)
+    lo, c = deriv_stencil(schemes.DERIV6, 32)
+    plan = cb.Plan(TRI, 32)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), axis, TRI, lo, c)
+    assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["deriv6", "interp6", "deriv10"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [64, 96, 192, 256])
+def test_fused_operators(gpu, scheme, axis, n):
+    shape = shape_with(axis, n)
+    f, _ = synth.random_modes(shape, seed=n + axis)
+    if scheme == "interp6":
+        bands, (lo, c) = INTERP, schemes.stencil_interp_c2s(schemes.INTERP6)
+    elif scheme == "deriv6":
+        bands, (lo, c) = TRI, deriv_stencil(schemes.DERIV6, n)
+    else:
+        bands, (lo, c) = PENTA, deriv_stencil(schemes.DERIV10, n)
+    plan = cb.Plan(bands, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
+    assert relerr(out, ref) <= 1e-12
+
+
+# ---------------------------------------------------------------- solves ---
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [5, 8, 32, 37, 128, 512, 613, 1024])
+def test_solve_random_rhs(gpu, bands, axis, n):
+    bd = TRI if bands == "tri" else PENTA
+    if n < 2 * len(bd) // 2 + 1:
+        pytest.skip("n too small")
+    shape = shape_with(axis, n, other=(9, 7))
+    b = synth.random_uniform(shape, seed=n * 3 + axis)
+    plan = cb.Plan(bd, n)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, bd)
+    assert relerr(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_solve_acyclic_and_per_row(gpu, axis):
+    n = 200
+    shape = shape_with(axis, n, other=(5, 6))
+    b = synth.random_uniform(shape, seed=axis)
+    bands = synth.random_bands(n, 2, seed=axis)
+    for cyclic in (True, False):
+        plan = cb.Plan(bands, n, per_row=True, cyclic=cyclic)
+        x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        ref = oracle.solve_axis(b.numpy(), axis, bands, per_row=True, cyclic=cyclic)
+        assert relerr(x, ref) <= 1e-12, cyclic
+
+
+def test_solve_in_place_and_strided_view(gpu):
+    n = 128
+    big = synth.random_uniform((10, 128, 2 * n), seed=5).to(gpu)
+    view = big[:, 3:99, ::2]  # non-contiguous: x stride 2
+    b = view.cpu().numpy()
+    plan = cb.Plan(TRI, n)
+    cb.solve(plan, view, 0, out=view)  # in place on a strided view
+    ref = oracle.solve_axis(np.ascontiguousarray(b), 0, TRI)
+    assert relerr(view.cpu().numpy(), ref) <= 1e-12
+    # rows outside the view are untouched
+    before = synth.random_uniform((10, 128, 2 * n), seed=5).numpy()
+    after = big.cpu().numpy()
+    mask = np.ones(after.shape, bool)
+    mask[:, 3:99, ::2] = False
+    assert np.array_equal(after[mask], before[mask])
+
+
+@pytest.mark.parametrize("P", [2, 3, 5, 16])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+@pytest.mark.parametrize("axis", [0, 2])
+def test_partitioned_lines(gpu, P, bands, axis):
+    bd = TRI if bands == "tri" else PENTA
+    n = 64 * P + 7
+    shape = shape_with(axis, n, other=(6, 5))
+    b = synth.random_uniform(shape, seed=P)
+    plan = cb.Plan(bd, n, partitions=P)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, bd)
+    assert relerr(x, ref) <= 1e-12
+
+
+def test_c3a_two_level_full_size(gpu):
+    """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
+    n = 8192
+    shape = (64, 64, n)
+    f, _ = synth.random_modes(shape, seed=3)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    b = oracle.stencil_axis(f.numpy(), 0, lo, c)
+    plan = cb.Plan(TRI, n, partitions=16)
+    x = cb.solve(plan, torch.from_numpy(b).to(gpu), 0).cpu().numpy()
+    ref = oracle.solve_axis(b, 0, TRI)
+    assert relerr(x, ref) <= 1e-12
+
+
+# --------------------------------------------------------- precision modes --
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_fp32_and_refinement(gpu, bands, axis):
+    bd = TRI if bands == "tri" else PENTA
+    n = 256
+    shape = shape_with(axis, n, other=(16, 8))
+    f, _ = synth.random_modes(shape, seed=7)
+    lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
+    ref = oracle.apply_axis(f.numpy(), axis, bd, lo, c)
+    st = cb.Stencil(lo, c)
+    p32 = cb.Plan(bd, n, precision="fp32")
+    e32 = relerr(cb.apply_derivative(p32, st, f.to(gpu), axis).cpu().numpy(), ref)
+    pr = cb.Plan(bd, n, precision="fp32_refine", refine_iters=2)
+    er = relerr(cb.apply_derivative(pr, st, f.to(gpu), axis).cpu().numpy(), ref)
+    print("fp32 %s: plain %.2e refined %.2e" % (bands, e32, er))
+    assert er <= 1e-12
+    assert e32 <= (1e-6 if bands == "tri" else 5e-6)
+
+
+def test_refinement_ragged_solve(gpu):
+    n = 613
+    b = synth.random_uniform((4, 3, n), seed=1)
+    plan = cb.Plan(PENTA, n, precision="fp32_refine", refine_iters=3)
+    x = cb.solve(plan, b.to(gpu), 0).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), 0, PENTA)
+    assert relerr(x, ref) <= 1e-12
+
+
+# ------------------------------------------------------------- stencil -----
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_rhs_stencil(gpu, axis):
+    shape = (10, 14, 18)
+    f = synth.random_uniform(shape, seed=axis)
+    lo, c = schemes.stencil_deriv_collocated(schemes.DERIV10, 0.1)
+    out = cb.rhs_stencil(cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.stencil_axis(f.numpy(), axis, lo, c)
+    assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ----------------------------------------------------------- error paths ---
+def test_errors_leave_output_untouched(gpu):
+    plan = cb.Plan(TRI, 32)
+    b = torch.ones((4, 4, 16), dtype=torch.float64, device=gpu)
+    out = torch.full_like(b, 7.0)
+    with pytest.raises(cb.CbError) as e:
+        cb.solve(plan, b, 0, out=out)  # n mismatch
+    assert e.value.status == cb.CB_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    host = cb.Plan(TRI, 16, host_only=True)
+    with pytest.raises(cb.CbError):
+        cb.solve(host, b, 0, out=out)

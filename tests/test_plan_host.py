@@ -1,0 +1,134 @@
+"""CPU checks of the host pre-factorisation (host-only plans, no GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import schemes
+from paper_2101_02286_amd import cb, synth
+from tests import plan_emulator
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    try:
+        cb.lib()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+def _bands(name):
+    return dict(tri=[1 / 3, 1.0, 1 / 3], penta=schemes.bands_collocated(schemes.DERIV10),
+                tri4=[0.25, 1.0, 0.25], interp=[0.3, 1.0, 0.3])[name]
+
+
+def test_abi_exports_every_declared_symbol():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "cb.h")).read()
+    declared = set(re.findall(r"\b(cb_[a-z_]+)\s*\(", hdr))
+    declared -= {"cb_plan_t"}
+    L = cb.lib()
+    missing = [s for s in declared if not hasattr(L, s)]
+    assert not missing, missing
+    assert declared >= set(cb.ABI_SYMBOLS)
+
+
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("n", [8, 11, 32, 37, 96, 192, 256, 512, 613, 1024])
+@pytest.mark.parametrize("cyclic", [True, False])
+def test_one_partition_plan_reproduces_oracle(name, n, cyclic):
+    bands = _bands(name)
+    p = cb.Plan(bands, n, cyclic=cyclic, host_only=True)
+    b = np.random.default_rng(n).standard_normal((3, n))
+    x = plan_emulator.solve(p, b)
+    ref = oracle.solve_lines(b, bands, cyclic=cyclic)
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("rpl", [4, 6, 8, 12, 16])
+def test_rows_per_lane_choices(rpl):
+    n = rpl * 32
+    p = cb.Plan(_bands("penta"), n, rows_per_lane=rpl, host_only=True)
+    assert p.info()["rows_per_lane"] == rpl
+    b = np.random.default_rng(rpl).standard_normal((2, n))
+    ref = oracle.solve_lines(b, _bands("penta"))
+    assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_per_row_bands():
+    n, r = 300, 2
+    bands = synth.random_bands(n, r, seed=4)
+    p = cb.Plan(bands, n, per_row=True, host_only=True)
+    assert not p.info()["uniform"]
+    b = np.random.default_rng(0).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands, per_row=True)
+    assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 7, 11, 15, 16])
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [True, False])
+def test_partitioned_plan_reproduces_oracle(P, name, cyclic):
+    n = 64 * P + 13
+    bands = _bands(name)
+    p = cb.Plan(bands, n, partitions=P, cyclic=cyclic, host_only=True)
+    b = np.random.default_rng(P).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands, cyclic=cyclic)
+    x = plan_emulator.solve(p, b)
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_step_counts_match_paper():
+    """Sec. 4: floor(log2 p) block-PCR steps; popcount(p)-1 detach steps."""
+    for P in range(2, 34):
+        info = cb.Plan([1 / 3, 1, 1 / 3], 40 * P, partitions=P, host_only=True).info()
+        assert info["red_pcr_steps"] == P.bit_length() - 1, P
+        assert info["red_detach_steps"] == bin(P).count("1") - 1, P
+        sched = cb.Plan([1 / 3, 1, 1 / 3], 40 * P, partitions=P, host_only=True).schedule()
+        # rows involved in detach/reattach: p - 2^floor(log2 p)
+        assert sum(len(l) for l in sched) == P - (1 << (P.bit_length() - 1)), P
+
+
+def test_eleven_row_example_schedule():
+    """Sec. 3 worked example (Figs. 6-7): 11 rows -> row 11 detached, then 9, 10."""
+    import os
+    gold = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "reduced_schedule_paper.txt")):
+        if line.startswith("example11"):
+            _, k, v = line.split()
+            gold[k] = v
+    p = cb.Plan([1 / 3, 1, 1 / 3], 11 * 40, partitions=11, host_only=True)
+    sched = [[d + 1 for d in lvl] for lvl in p.schedule()]  # 1-based as in the paper
+    assert sched[0] == [int(v) for v in gold["detached_level0"].split(",")]
+    assert sched[1] == [int(v) for v in gold["detached_level1"].split(",")]
+    assert all(len(l) == 0 for l in sched[2:])
+    info = p.info()
+    assert info["red_pcr_steps"] == int(gold["pcr_steps"])
+    assert info["red_detach_steps"] == int(gold["detach_steps"])
+
+
+def test_interior_levels():
+    """Sec. 4: ceil(log2 N_i) generalized-PCR steps for an interior block of N_i rows."""
+    for n, rpl in ((512, 8), (512, 16), (384, 12), (96, 6)):
+        info = cb.Plan([1 / 3, 1, 1 / 3], n, rows_per_lane=rpl, host_only=True).info()
+        assert info["interior_levels"] == int(np.ceil(np.log2(rpl - 1)))
+        assert info["lane_levels"] == int(np.log2(n // rpl))
+
+
+def test_singular_matrix_rejected():
+    with pytest.raises(cb.CbError) as e:
+        cb.Plan([0.5, 1.0, 0.5], 64, host_only=True)
+    assert e.value.status == cb.CB_ERR_SINGULAR
+    cb.Plan([0.5, 1.0, 0.5], 63, host_only=True)  # odd n is regular
+
+
+def test_bad_descriptors():
+    with pytest.raises(cb.CbError) as e:
+        cb.Plan([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0], 64, host_only=True)
+    assert e.value.status == cb.CB_ERR_UNSUPPORTED
+    with pytest.raises(cb.CbError):
+        cb.Plan([1 / 3, 1, 1 / 3], 2, host_only=True)
+    with pytest.raises(cb.CbError):
+        cb.Plan([1 / 3, 1, 1 / 3], 64, rows_per_lane=5, host_only=True)
