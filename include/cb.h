@@ -135,17 +135,29 @@ typedef struct {
   cb_grid grid;
   int32_t axis;
   const double *in;          /* device: b (solve) or f (derivative) */
-  double *out;               /* device */
+  double *out;               /* device; must not overlap `in` or another item's out */
 } cb_batch_item;
 
-/* Run many items in ONE persistent kernel launch over a device work table
- * (lines of uneven grids share the launch).  All items must use plans of the
- * same precision and half bandwidth r; items may differ in n, axis, grid and
- * plan.  `workspace` is a device buffer of at least cb_batch_workspace_size()
- * bytes, owned by the caller and not used concurrently by another call;
- * `max_ctas` caps the number of resident workgroups (0 = one wave of the
- * whole chip). */
+/* Batched execution: the lines of many items -- uneven grids, any axes,
+ * different plans -- run in ONE persistent kernel launch that takes tiles
+ * from a device work queue.  Every plan in a batch must have partitions = 1,
+ * the same r, the same rows_per_lane (8 or 16) and the same arithmetic
+ * (FP64, or FP32 with or without refinement); n, axis, grid, stencil and
+ * refinement count may differ.  Plans must be cyclic when a stencil is given.
+ *
+ * `workspace` is a caller-owned DEVICE buffer of at least
+ * cb_batch_workspace_size(n_items) bytes holding the queue and work table.
+ * cb_batch_build validates the items and writes the table (it waits for the
+ * copy to finish).  cb_batch_launch enqueues the persistent kernel only: it
+ * allocates nothing, copies nothing and leaves the queue reset when it
+ * finishes, so it may be captured in a HIP graph and replayed.  Launches
+ * that share a workspace must not overlap in time.  `max_ctas` caps the
+ * resident workgroups (0 = as many as fit on the device at once). */
 size_t cb_batch_workspace_size(int32_t n_items);
+cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace,
+                         size_t workspace_bytes, void *stream);
+cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream);
+/* cb_batch_build followed by cb_batch_launch. */
 cb_status cb_solve_batched(const cb_batch_item *items, int32_t n_items, void *workspace,
                            size_t workspace_bytes, int32_t max_ctas, void *stream);
 

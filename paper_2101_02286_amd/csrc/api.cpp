@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -20,6 +22,10 @@ namespace cb {
 namespace {
 
 thread_local std::string g_err;
+
+// kernel selection (r, rows_per_lane, fp32) of each built batch workspace
+std::mutex g_batch_mu;
+std::map<void *, std::array<int, 3>> g_batch_sel;
 
 cb_status fail(cb_status s, const std::string &m) {
   g_err = m;
@@ -393,17 +399,123 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
   return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
 }
 
-size_t cb_batch_workspace_size(int32_t n_items) { return n_items > 0 ? (size_t)n_items * 256 + 256 : 256; }
+size_t cb_batch_workspace_size(int32_t n_items) {
+  return 256 + (size_t)(n_items > 0 ? n_items : 0) * sizeof(BatchItemDev);
+}
+
+cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
+                         void *stream) {
+  if (!items || n_items <= 0) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: no items");
+  if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace is NULL");
+  if (workspace_bytes < cb_batch_workspace_size(n_items))
+    return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace too small");
+  std::vector<BatchItemDev> tab(n_items);
+  int R0 = -1, M0 = -1, fp0 = -1;
+  int64_t tiles = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const cb_batch_item &it = items[i];
+    cb_status s = check_plan_for_solve(it.plan);
+    if (s) return s;
+    const Plan &p = it.plan->p;
+    if (p.P != 1) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: plans must have partitions = 1");
+    const int fp = p.precision != CB_FP64;
+    if (R0 < 0) {
+      R0 = p.R;
+      M0 = p.M;
+      fp0 = fp;
+    } else if (p.R != R0 || p.M != M0 || fp != fp0) {
+      return fail(CB_ERR_INVALID_ARG, "cb_batch_build: plans differ in r, rows_per_lane or precision");
+    }
+    if (p.M != 8 && p.M != 16) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: rows_per_lane must be 8 or 16");
+    Geo g;
+    if ((s = geometry(&it.grid, it.axis, g))) return s;
+    if (g.n != p.n) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: grid extent differs from plan n");
+    if (!it.in || !it.out) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: NULL data pointer");
+    if (overlap(it.in, it.out, span_elems(&it.grid)))
+      return fail(CB_ERR_INVALID_ARG, "cb_batch_build: in and out overlap");
+    if (it.stencil) {
+      if ((s = check_stencil(it.stencil))) return s;
+      if (!p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: a stencil needs a cyclic plan");
+    }
+    const int L = p.L;
+    if (L > kBatchThreads) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: line needs too many lanes");
+    const int W = kBatchThreads / L;
+    BatchItemDev &d = tab[i];
+    std::memset(&d, 0, sizeof(d));
+    LineArgs &a = d.a;
+    a.in = it.in;
+    a.out = it.out;
+    a.nlines = g.nlines;
+    a.nu = g.nu;
+    a.su = g.su;
+    a.sv = g.sv;
+    a.rs = g.rs;
+    a.lgL = ilog2(L);
+    a.lgW = ilog2(W);
+    a.block_sync = 1;
+    a.refine_iters = p.refine_iters;
+    a.seg = p.segdev_host[0];
+    if (it.stencil) stencil_q(it.stencil, a.stc);
+    else a.stc[3] = 1.0;  // identity stencil: b = input
+    for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
+    a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
+    d.mode = g.rs == 1 ? MODE_X : MODE_S;
+    d.tile_begin = tiles;
+    tiles += (g.nlines + W - 1) / W;
+  }
+  for (int i = 0; i < n_items; ++i)
+    for (int j = i + 1; j < n_items; ++j)
+      if (overlap(items[i].out, items[j].out,
+                  std::max(span_elems(&items[i].grid), span_elems(&items[j].grid))))
+        return fail(CB_ERR_INVALID_ARG, "cb_batch_build: outputs of two items overlap");
+  std::vector<char> host(cb_batch_workspace_size(n_items), 0);
+  BatchHdr h;
+  std::memset(&h, 0, sizeof(h));
+  h.n_items = n_items;
+  h.total_tiles = tiles;
+  std::memcpy(host.data(), &h, sizeof(h));
+  std::memcpy(host.data() + 256, tab.data(), sizeof(BatchItemDev) * tab.size());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "cb_batch_build: copy");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batch_sel[workspace] = {R0, M0, fp0};
+  return CB_OK;
+}
+
+cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
+  if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace is NULL");
+  std::array<int, 3> sel;
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto itr = g_batch_sel.find(workspace);
+    if (itr == g_batch_sel.end()) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace was not built");
+    sel = itr->second;
+  }
+  const void *fn = find_batch_kernel(sel[0], sel[1], sel[2]);
+  if (!fn) return fail(CB_ERR_UNSUPPORTED, "cb_batch_launch: no kernel for this batch");
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds = (size_t)kBatchThreads * 2 * 3 * sizeof(double);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds);
+  if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
+  int ctas = std::max(1, ncu * std::max(per_cu, 1));
+  if (max_ctas > 0) ctas = std::min(ctas, (int)max_ctas);
+  BatchHdr *hdr = static_cast<BatchHdr *>(workspace);
+  const BatchItemDev *items = reinterpret_cast<const BatchItemDev *>(static_cast<char *>(workspace) + 256);
+  void *args[] = {&hdr, &items};
+  e = hipLaunchKernel(fn, dim3(ctas), dim3(kBatchThreads), args, lds, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
+  return CB_OK;
+}
 
 cb_status cb_solve_batched(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
                            int32_t max_ctas, void *stream) {
-  (void)items;
-  (void)n_items;
-  (void)workspace;
-  (void)workspace_bytes;
-  (void)max_ctas;
-  (void)stream;
-  return fail(CB_ERR_UNSUPPORTED, "cb_solve_batched: not built yet");
+  cb_status s = cb_batch_build(items, n_items, workspace, workspace_bytes, stream);
+  if (s) return s;
+  return cb_batch_launch(workspace, max_ctas, stream);
 }
 
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {

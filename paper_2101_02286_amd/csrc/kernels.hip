@@ -19,8 +19,7 @@ namespace cb {
 //         W*8-byte segment.
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, int MODE, int Q, bool UNI>
-__global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, double *smem) {
   constexpr int RS = (Q > R ? Q : R);
   LanePos p;
   p.tid = threadIdx.x;
@@ -38,7 +37,7 @@ __global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
   }
   Xchg xc{smem, RS, (int)blockDim.x, 0, a.block_sync != 0};
   const SegDev &sg = a.seg;
-  const int64_t line = (int64_t)blockIdx.x * p.W + p.li;
+  const int64_t line = tile * p.W + p.li;
   const bool active = line < a.nlines;
   const int64_t lu = active ? line % a.nu : 0, lv = active ? line / a.nu : 0;
   const int64_t base = lu * a.su + lv * a.sv;
@@ -131,6 +130,56 @@ __global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
 #pragma unroll
     for (int k = 0; k < M; ++k)
       if (UNI || k < m) __builtin_nontemporal_store(x64[k], out + k * rs);
+  }
+}
+
+template <int R, int M, typename T, int MODE, int Q, bool UNI>
+__global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
+  extern __shared__ double smem[];
+  line_tile<R, M, T, MODE, Q, UNI>(a, (int64_t)blockIdx.x, smem);
+}
+
+// ------------------------------------------------------------------------
+// Persistent batched launch: the grid takes tiles from a device work queue
+// that spans the lines of many (grid, axis, plan) items of uneven sizes.
+// Every item runs with the fused stencil (an identity stencil for plain
+// solves), the general lane layout and its own tile shape.  A workgroup
+// leaves when the queue is exhausted; the last one to leave resets the queue
+// so the launch can be replayed (e.g. from a captured graph) without a
+// memset.
+// ------------------------------------------------------------------------
+template <int R, int M, typename T>
+__global__ __launch_bounds__(512) void k_batched(BatchHdr *hdr, const BatchItemDev *items) {
+  extern __shared__ double smem[];
+  __shared__ int64_t s_tile;
+  const int64_t total = hdr->total_tiles;
+  const int nitems = hdr->n_items;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&hdr->next_tile, 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= total) break;
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchItemDev &it = items[lo];
+    if (it.mode == MODE_X)
+      line_tile<R, M, T, MODE_X, 3, false>(it.a, t - it.tile_begin, smem);
+    else
+      line_tile<R, M, T, MODE_S, 3, false>(it.a, t - it.tile_begin, smem);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&hdr->done, 1u);
+    if (prev == gridDim.x - 1) {
+      atomicExch(&hdr->next_tile, 0ull);
+      atomicExch(&hdr->done, 0u);
+      __threadfence();
+    }
   }
 }
 
@@ -365,5 +414,18 @@ const WgKernel *find_wg_kernel(int R, int M, int mode) {
 }
 
 const void *stencil_kernel() { return (const void *)&k_stencil; }
+
+#define CB_BATCH_INST(R, M, T) {R, M, sizeof(T) == 8 ? 0 : 1, (const void *)&k_batched<R, M, T>}
+static const BatchKernel kBatchKernels[] = {
+    CB_BATCH_INST(1, 8, double), CB_BATCH_INST(2, 8, double), CB_BATCH_INST(1, 8, float), CB_BATCH_INST(2, 8, float),
+    CB_BATCH_INST(1, 16, double), CB_BATCH_INST(2, 16, double), CB_BATCH_INST(1, 16, float),
+    CB_BATCH_INST(2, 16, float),
+};
+
+const void *find_batch_kernel(int R, int M, int fp32) {
+  for (const auto &k : kBatchKernels)
+    if (k.R == R && k.M == M && k.fp32 == fp32) return k.fn;
+  return nullptr;
+}
 
 }  // namespace cb

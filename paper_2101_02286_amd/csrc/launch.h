@@ -53,7 +53,27 @@ struct WgKernel {
   const void *fn_a, *fn_c;
 };
 
+// Persistent batched launch: queue header and one work-table entry per item.
+struct BatchHdr {
+  unsigned long long next_tile;  // next tile to hand out
+  unsigned int done;             // workgroups that have left
+  int n_items;
+  int64_t total_tiles;
+};
+struct BatchItemDev {
+  LineArgs a;
+  int64_t tile_begin;  // first global tile index of this item
+  int mode;
+  int pad;
+};
+struct BatchKernel {
+  int R, M, fp32;
+  const void *fn;
+};
+constexpr int kBatchThreads = 512;
+
 const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
+const void *find_batch_kernel(int R, int M, int fp32);
 const WgKernel *find_wg_kernel(int R, int M, int mode);
 const void *stencil_kernel();
 

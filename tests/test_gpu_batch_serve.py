@@ -1,0 +1,138 @@
+"""GPU tests of the batched persistent launch, its graph replay, and the
+continuous-batching server (each result alone equals the result in the mix)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import schemes
+from paper_2101_02286_amd import cb, synth
+from paper_2101_02286_amd.serve import GpuExecutor, Server, poisson_requests
+
+pytestmark = pytest.mark.gpu
+
+TRI = schemes.bands_collocated(schemes.DERIV6)
+PENTA = schemes.bands_collocated(schemes.DERIV10)
+
+
+def relerr(x, ref):
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def stencil_for(scheme, n):
+    s = schemes.DERIV6 if scheme == "tri6" else schemes.DERIV10
+    lo, c = schemes.stencil_deriv_collocated(s, 2 * math.pi / n)
+    return lo, c
+
+
+def batch(items, stream=None):
+    arr = (cb.BatchItem * len(items))()
+    keep = []
+    for i, (plan, st, f, out, axis) in enumerate(items):
+        arr[i].plan = plan.h
+        arr[i].stencil = cb.ctypes.pointer(st.c) if st is not None else None
+        arr[i].grid = cb.grid_of(f)
+        arr[i].axis = axis
+        arr[i].inp = f.data_ptr()
+        arr[i].out = out.data_ptr()
+        keep.append(st)
+    need = cb.lib().cb_batch_workspace_size(len(items))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    s = stream or torch.cuda.current_stream()
+    cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), need,
+                                      cb.ctypes.c_void_p(s.cuda_stream)))
+    return ws
+
+
+def launch(ws, stream=None, max_ctas=0):
+    s = stream or torch.cuda.current_stream()
+    cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), max_ctas,
+                                       cb.ctypes.c_void_p(s.cuda_stream)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_uneven_grids_one_launch(gpu, precision):
+    shapes = [(16, 16, 16), (32, 24, 40), (48, 48, 48), (96, 32, 16), (24, 128, 8), (64, 20, 36)]
+    items, refs = [], []
+    for gi, (nx, ny, nz) in enumerate(shapes):
+        f, _ = synth.random_modes((nz, ny, nx), seed=gi)
+        fd = f.to(gpu)
+        for axis in range(3):
+            n = (nx, ny, nz)[axis]
+            lo, c = stencil_for("tri6", n)
+            plan = cb.Plan(TRI, n, precision=precision, rows_per_lane=8)
+            out = torch.empty_like(fd)
+            items.append((plan, cb.Stencil(lo, c), fd, out, axis))
+            refs.append(oracle.apply_axis(f.numpy(), axis, TRI, lo, c))
+    ws = batch(items)
+    launch(ws, max_ctas=7)  # few workgroups: each loops over many tiles
+    torch.cuda.synchronize()
+    for (plan, st, fd, out, axis), ref in zip(items, refs):
+        assert relerr(out.cpu().numpy(), ref) <= 1e-12
+
+
+def test_batched_solve_items_and_penta(gpu):
+    items, refs = [], []
+    for i, n in enumerate((37, 100, 256, 613)):
+        b = synth.random_uniform((5, 3, n), seed=i).to(gpu)
+        plan = cb.Plan(PENTA, n, rows_per_lane=16)
+        out = torch.empty_like(b)
+        items.append((plan, None, b, out, 0))
+        refs.append(oracle.solve_axis(b.cpu().numpy(), 0, PENTA))
+    launch(batch(items))
+    torch.cuda.synchronize()
+    for it, ref in zip(items, refs):
+        assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
+
+
+def test_graph_replay_of_batched_launch(gpu):
+    """Captured launch replayed several times with eager work in between."""
+    f, _ = synth.random_modes((24, 40, 32), seed=4)
+    fd = f.to(gpu)
+    items = []
+    for axis in range(3):
+        n = fd.shape[2 - axis]
+        lo, c = stencil_for("tri6", n)
+        items.append((cb.Plan(TRI, n, rows_per_lane=8), cb.Stencil(lo, c), fd, torch.empty_like(fd), axis))
+    s = torch.cuda.Stream()
+    ws = batch(items, stream=s)
+    launch(ws, stream=s)
+    s.synchronize()
+    eager = [it[3].clone() for it in items]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        launch(ws, stream=s)
+    for rep in range(4):
+        for it in items:
+            it[3].fill_(float(rep))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for it, e in zip(items, eager):
+            assert torch.equal(it[3], e), rep
+
+
+def test_server_results_same_alone_and_in_mix(gpu):
+    results = {}
+
+    def keep(r, f, out):
+        results[r.rid] = (f.cpu().numpy(), out.cpu().numpy())
+
+    reqs = poisson_requests(14, rate_hz=400.0, seed=5, side_lo=12, side_hi=96)
+    ex = GpuExecutor(slots=3, on_result=keep)
+    srv = Server(ex, hbm_budget=6 * max(r.mem for r in reqs), slots=3, max_batch=6)
+    st = srv.run(reqs)
+    assert st["requests"] == 14
+    for r in reqs:
+        f, out_mix = results[r.rid]
+        plan, stc = ex.plan(r.scheme, r.n)
+        fd = torch.from_numpy(f).to(gpu)
+        alone = torch.empty_like(fd)
+        launch(batch([(plan, stc, fd, alone, r.axis)]))
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.cpu().numpy(), out_mix), r.rid  # bitwise
+        bands = TRI if r.scheme == "tri6" else PENTA
+        ref = oracle.apply_axis(f, r.axis, bands, stc.lo, stc.coefs)
+        assert relerr(out_mix, ref) <= 1e-12, r.rid
