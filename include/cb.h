@@ -80,6 +80,14 @@ typedef struct {
   int32_t host_only;     /* 1: factorise on the host only (no device memory is
                             touched); such a plan can be inspected with
                             cb_plan_get_* but solve calls reject it */
+  /* Launch tuning (0 = automatic).  rows_per_lane above sets where the
+   * reduction switches from registers (ceil(log2(rows_per_lane - r)) levels
+   * of generalized PCR per lane) to LDS (log2(lanes) block-PCR levels). */
+  int32_t lines_per_wg;   /* lines per workgroup: 1..1024, power of two, with
+                             lines_per_wg * lanes <= 1024 */
+  int32_t block_barriers; /* 0: lane exchanges of a line that lies inside one
+                             wavefront use wavefront-local ordering only;
+                             1: always workgroup barriers */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +

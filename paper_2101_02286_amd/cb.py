@@ -16,7 +16,8 @@ _lib = None
 CB_OK, CB_ERR_INVALID_ARG, CB_ERR_UNSUPPORTED, CB_ERR_SINGULAR, CB_ERR_OOM, CB_ERR_HIP = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
 ABI_SYMBOLS = ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
-               "cb_batch_workspace_size", "cb_solve_batched", "cb_plan_get_info",
+               "cb_batch_workspace_size", "cb_batch_build", "cb_batch_launch", "cb_solve_batched",
+               "cb_plan_get_info",
                "cb_plan_get_schedule", "cb_plan_get_array", "cb_last_error")
 
 
@@ -30,7 +31,8 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("n", ctypes.c_int32), ("bands", ctypes.POINTER(ctypes.c_double)),
                 ("per_row", ctypes.c_int32), ("cyclic", ctypes.c_int32), ("partitions", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
-                ("rows_per_lane", ctypes.c_int32), ("host_only", ctypes.c_int32)]
+                ("rows_per_lane", ctypes.c_int32), ("host_only", ctypes.c_int32),
+                ("lines_per_wg", ctypes.c_int32), ("block_barriers", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -70,12 +72,15 @@ def lib():
         L.cb_batch_workspace_size.argtypes = [i32]
         L.cb_batch_workspace_size.restype = ctypes.c_size_t
         L.cb_solve_batched.argtypes = [ctypes.POINTER(BatchItem), i32, vp, ctypes.c_size_t, i32, vp]
+        L.cb_batch_build.argtypes = [ctypes.POINTER(BatchItem), i32, vp, ctypes.c_size_t, vp]
+        L.cb_batch_launch.argtypes = [vp, i32, vp]
         L.cb_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.cb_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
         L.cb_plan_get_array.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(i64)]
         L.cb_last_error.restype = ctypes.c_char_p
         for f in ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
-                  "cb_solve_batched", "cb_plan_get_info", "cb_plan_get_schedule", "cb_plan_get_array"):
+                  "cb_solve_batched", "cb_batch_build", "cb_batch_launch", "cb_plan_get_info",
+                  "cb_plan_get_schedule", "cb_plan_get_array"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -101,14 +106,14 @@ class Plan:
     """Pre-factorised compact banded matrix (cb_plan)."""
 
     def __init__(self, bands, n, cyclic=True, partitions=1, precision="fp64", refine_iters=0,
-                 rows_per_lane=0, per_row=False, host_only=False):
+                 rows_per_lane=0, per_row=False, host_only=False, lines_per_wg=0, block_barriers=0):
         import numpy as np
         b = np.ascontiguousarray(np.asarray(bands, dtype=np.float64))
         r = (b.shape[-1] - 1) // 2
         self._bands = b
         d = PlanDesc(r, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(per_row), int(cyclic),
                      int(partitions), PRECISIONS[precision], int(refine_iters), int(rows_per_lane),
-                     int(host_only))
+                     int(host_only), int(lines_per_wg), int(block_barriers))
         h = ctypes.c_void_p()
         _check(lib().cb_plan(ctypes.byref(d), ctypes.byref(h)))
         self.h = h

@@ -198,15 +198,19 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const void *fn = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni);
   if (!fn) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
   const int L = sp.L;
-  int NT;
-  if (mode == MODE_X) {
-    NT = std::max(L, 256);
-  } else {
-    NT = std::min(1024, std::max(L, 16 * L));
-  }
-  NT = std::min(NT, 1024);
   if (L > 1024) return fail(CB_ERR_UNSUPPORTED, "line needs more than 1024 lanes");
-  const int W = NT / L;
+  int W;
+  if (p.desc.lines_per_wg > 0) {
+    W = p.desc.lines_per_wg;
+  } else if (mode == MODE_X) {
+    W = std::max(1, 256 / L);
+  } else {
+    W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
+  }
+  const int NT = W * L;
+  // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
+  // one wavefront and its exchanges need no workgroup barrier
+  const bool wave_local = mode == MODE_X && L <= 64 && (64 % L == 0) && p.desc.block_barriers == 0;
   LineArgs a;
   std::memset(&a, 0, sizeof(a));
   a.in = in;
@@ -218,7 +222,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   a.rs = g.rs;
   a.lgL = ilog2(L);
   a.lgW = ilog2(W);
-  a.block_sync = 1;
+  a.block_sync = wave_local ? 0 : 1;
   a.refine_iters = p.refine_iters;
   a.seg = p.segdev_host[0];
   if (st) stencil_q(st, a.stc);

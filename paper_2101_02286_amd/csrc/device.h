@@ -25,6 +25,14 @@ namespace cb {
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
+// Plan coefficients are read-only for the whole launch.  Reading them through
+// the constant address space lets uniform reads become scalar (s_load) reads
+// that land in SGPRs instead of occupying vector registers.
+template <typename T>
+__device__ __forceinline__ T cld(const T *p) {
+  return *reinterpret_cast<const __attribute__((address_space(4))) T *>(reinterpret_cast<uintptr_t>(p));
+}
+
 constexpr int ceil_log2_c(int v) { return v <= 1 ? 0 : 1 + ceil_log2_c((v + 1) / 2); }
 
 template <typename T> __device__ __forceinline__ const T *coef_of(const SegDev &s);
@@ -117,8 +125,8 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
       const T *kj = cf + off.k + (t * N + j) * 2 * R;
 #pragma unroll
       for (int q = 1; q <= R; ++q) {
-        if (j - q * s >= 0) acc -= kj[R - q] * y[j - q * s];
-        if (j + q * s < N) acc -= kj[R + q - 1] * y[j + q * s];
+        if (j - q * s >= 0) acc -= cld(kj + R - q) * y[j - q * s];
+        if (j + q * s < N) acc -= cld(kj + R + q - 1) * y[j + q * s];
       }
       yn[j] = acc;
     }
@@ -126,7 +134,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     for (int j = 0; j < N; ++j) y[j] = yn[j];
   }
 #pragma unroll
-  for (int j = 0; j < N; ++j) y[j] *= cf[off.dinv + j];
+  for (int j = 0; j < N; ++j) y[j] *= cld(cf + off.dinv + j);
 
   // ---- interface RHS b^_l = b~_l - L~_l y_{l-1} - U~_l y_l (Eq. (21)) ----
   const int nl = m - R;  // real interior rows of this lane
@@ -142,7 +150,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
   for (int a = 0; a < R; ++a) {
     T acc = v[a];
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc -= cf[off.Lt + a * R + c] * yprev[c] + cf[off.Ut + a * R + c] * y[c];
+    for (int c = 0; c < R; ++c) acc -= cld(cf + off.Lt + a * R + c) * yprev[c] + cld(cf + off.Ut + a * R + c) * y[c];
     xt[a] = acc;
   }
 
@@ -163,7 +171,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     for (int a = 0; a < R; ++a) {
       T acc = xt[a];
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc -= mu[a * R + c] * xp[c] + ml[a * R + c] * xm[c];
+      for (int c = 0; c < R; ++c) acc -= cld(mu + a * R + c) * xp[c] + cld(ml + a * R + c) * xm[c];
       xn[a] = acc;
     }
 #pragma unroll
@@ -176,7 +184,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     for (int a = 0; a < R; ++a) {
       T acc = (T)0;
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc += w[a * R + c] * xt[c];
+      for (int c = 0; c < R; ++c) acc += cld(w + a * R + c) * xt[c];
       xn[a] = acc;
     }
 #pragma unroll
@@ -193,7 +201,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     T acc = y[j];
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      acc -= cf[off.S + j * R + c] * xt[c] + cf[off.Rm + j * R + c] * xnext[c];
+      acc -= cld(cf + off.S + j * R + c) * xt[c] + cld(cf + off.Rm + j * R + c) * xnext[c];
     v[R + j] = acc;
   }
 #pragma unroll

@@ -628,6 +628,11 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     msg = "rows_per_lane must be 0, 4, 6, 8, 12 or 16";
     return CB_ERR_UNSUPPORTED;
   }
+  if (d.lines_per_wg < 0 || d.lines_per_wg > 1024 || (d.lines_per_wg & (d.lines_per_wg - 1)) ||
+      d.block_barriers < 0 || d.block_barriers > 1) {
+    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1";
+    return CB_ERR_INVALID_ARG;
+  }
   const int R = d.r, n = d.n, W = 2 * R + 1;
   const int P = d.partitions <= 0 ? 1 : d.partitions;
   if (P > 64) {
@@ -675,6 +680,10 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     p.M = p.segs[0].M;
     p.L = p.segs[0].L;
     p.wg_start = {0, n};
+    if (d.lines_per_wg && d.lines_per_wg * p.L > 1024) {
+      msg = "lines_per_wg * lanes exceeds 1024 threads";
+      return CB_ERR_INVALID_ARG;
+    }
     return CB_OK;
   }
   // P > 1: workgroup partitions, each with R interface rows and an interior
