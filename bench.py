@@ -123,8 +123,154 @@ def headline(args):
     return res
 
 
+def _time_launches(fn, steps, warmup, stream):
+    """Run fn() warmup + steps times; return per-launch HIP-event durations (ms) and wall seconds."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return np.array([a.elapsed_time(b) for a, b in evs]), wall
+
+
+def mode_two_level(args):
+    """n = 8192 lines (64 x 64 of them) split into P = 16 workgroup partitions."""
+    dev = torch.device("cuda:0")
+    n, P = 8192, 16
+    bands, (a, b) = tri6()
+    plan = cb.Plan(bands, n, partitions=P)
+    f, _ = synth.random_modes((64, 64, n), seed=3, device=dev)
+    rhs = cb.rhs_stencil(deriv_stencil(n, a, b), f, 0)
+    x = torch.empty_like(rhs)
+    stream = torch.cuda.current_stream()
+    dur, wall = _time_launches(lambda: cb.solve(plan, rhs, 0, out=x, stream=stream), args.steps, args.warmup, stream)
+    dof = rhs.numel()
+    ms = float(dur.mean())
+    return {"metric": "GDOF/s, cyclic tridiagonal n=8192 two-level (P=16 workgroup partitions)",
+            "value": round(dof / (ms * 1e-3) / 1e9, 3), "unit": "GDOF/s", "ms_per_solve": round(ms, 4),
+            "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1),
+            "hbm_gbs_moved": round(24 * dof / (ms * 1e-3) / 1e9, 1),
+            "p50_ms": round(float(np.percentile(dur, 50)), 4), "p99_ms": round(float(np.percentile(dur, 99)), 4),
+            "config": {"workload": "64x64 lines of n=8192, P=16", "partitions": P}, "dtype": "f64"}
+
+
+def mode_penta_z(args):
+    """512^3 tenth-order pentadiagonal compact derivative along z."""
+    dev = torch.device("cuda:0")
+    n = args.n
+    a, b, c = 17 / 12, 101 / 150, 1 / 100
+    bands = [1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20]
+    h = 2 * math.pi / n
+    st = cb.Stencil(-3, [-c / (6 * h), -b / (4 * h), -a / (2 * h), 0.0, a / (2 * h), b / (4 * h), c / (6 * h)])
+    plan = cb.Plan(bands, n)
+    f, _ = synth.random_modes((n, n, n), seed=1, device=dev)
+    out = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for ax in range(3):
+        dur, wall = _time_launches(lambda: cb.apply_derivative(plan, st, f, ax, out=out, stream=stream),
+                                   args.steps, args.warmup, stream)
+        ms = float(dur.mean())
+        res["xyz"[ax]] = {"ms": round(ms, 4), "gdofs": round(n ** 3 / (ms * 1e-3) / 1e9, 2),
+                          "hbm_gbs_algorithmic": round(16 * n ** 3 / (ms * 1e-3) / 1e9, 1)}
+    return {"metric": "GDOF/s, %d^3 tenth-order pentadiagonal compact derivative" % n, "per_direction": res,
+            "dtype": "f64", "config": {"workload": "%d^3, alpha=1/2 beta=1/20" % n}}
+
+
+def mode_batched(args):
+    """12 uneven periodic grids x 3 axes in one persistent launch: FP32+refinement vs FP64."""
+    dev = torch.device("cuda:0")
+    shapes = synth.grid_batch_shapes(seed=0, count=12)
+    bands, (a, b) = tri6()
+    fields = []
+    for gi, (nx, ny, nz) in enumerate(shapes):
+        f, _ = synth.random_modes((nz, ny, nx), seed=gi, device=dev)
+        fields.append(f)
+    out = {}
+    for prec in ("fp64", "fp32_refine"):
+        plans, items = {}, []
+        for f in fields:
+            for ax in range(3):
+                n = f.shape[2 - ax]
+                if n not in plans:
+                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=2, rows_per_lane=8),
+                                deriv_stencil(n, a, b))
+                items.append((plans[n][0], plans[n][1], f, torch.empty_like(f), ax))
+        arr = (cb.BatchItem * len(items))()
+        for i, (pl, st, f, o, ax) in enumerate(items):
+            arr[i].plan = pl.h
+            arr[i].stencil = cb.ctypes.pointer(st.c)
+            arr[i].grid = cb.grid_of(f)
+            arr[i].axis = ax
+            arr[i].inp = f.data_ptr()
+            arr[i].out = o.data_ptr()
+        need = cb.lib().cb_batch_workspace_size(len(items))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream()
+        cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), need,
+                                          cb.ctypes.c_void_p(stream.cuda_stream)))
+        launch = lambda: cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), 0,
+                                                            cb.ctypes.c_void_p(stream.cuda_stream)))
+        dur, wall = _time_launches(launch, args.steps, args.warmup, stream)
+        dof = sum(f.numel() for f in fields) * 3
+        ms = float(dur.mean())
+        out[prec] = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
+                     "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1), "items": len(items),
+                     "outputs": [it[3] for it in items]}
+    # accuracy of the FP32+refinement outputs against the FP64 outputs
+    worst = 0.0
+    for o64, o32 in zip(out["fp64"].pop("outputs"), out["fp32_refine"].pop("outputs")):
+        worst = max(worst, float(((o64 - o32).abs().max() / o64.abs().max()).item()))
+    return {"metric": "GDOF/s, 12 uneven grids x 3 axes in one persistent launch", "fp64": out["fp64"],
+            "fp32_refine2": out["fp32_refine"], "max_rel_diff_fp32refine_vs_fp64": worst,
+            "config": {"workload": "grids %s" % shapes}}
+
+
+def mode_serve(args):
+    """Poisson request stream served with continuous batching (FP32+refinement)."""
+    from paper_2101_02286_amd.serve import GpuExecutor, Server, poisson_requests
+    res = []
+    for rate in args.rates:
+        reqs = poisson_requests(args.requests, rate_hz=rate, seed=11, max_points=args.max_points)
+        ex = GpuExecutor(slots=4)
+        for r in reqs:  # factorise every plan before the clock starts
+            ex.plan(r.scheme, r.n)
+        srv = Server(ex, hbm_budget=args.budget_gb * (1 << 30), slots=4, max_batch=16)
+        st = srv.run(reqs)
+        st["rate_hz"] = rate
+        res.append(st)
+    return {"metric": "served p50/p99 latency and GDOF/s", "runs": res,
+            "config": {"workload": "Poisson stream, sides log-uniform [32,1024], <= %.2g points, "
+                                   "tri6/penta10, FP32+refinement(2)" % args.max_points}}
+
+
+def mode_copy(args):
+    """Plain device copy of a known size (reference for the HBM byte counters)."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    dur, wall = _time_launches(lambda: b.copy_(a), args.steps, args.warmup, stream)
+    ms = float(dur.mean())
+    return {"metric": "device copy", "bytes_read": a.numel() * 8, "bytes_written": a.numel() * 8,
+            "ms": round(ms, 4), "gbs": round(2 * a.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="headline",
+                    choices=["headline", "two_level", "penta_z", "batched", "serve", "copy"])
+    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 800.0])
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--max-points", type=float, default=1.5e8)
+    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -136,7 +282,9 @@ def main():
         print("this benchmark runs on one GPU only (the multi-GPU split is a design, not part of this build)",
               file=sys.stderr)
         sys.exit(2)
-    res = headline(args)
+    fn = {"headline": headline, "two_level": mode_two_level, "penta_z": mode_penta_z, "batched": mode_batched,
+          "serve": mode_serve, "copy": mode_copy}[args.mode]
+    res = fn(args)
     print(json.dumps(res), flush=True)
 
 

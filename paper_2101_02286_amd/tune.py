@@ -1,0 +1,108 @@
+"""Autotuner for the line-solver launch shape.
+
+For one (bands, n, precision, grid shape, axis) it times every valid choice of
+  * rows_per_lane -- where the reduction switches from registers (generalized
+    PCR inside a lane, ceil(log2(rows_per_lane - r)) levels) to LDS (block
+    PCR across lanes, log2(lanes) levels),
+  * lines_per_wg  -- lines per workgroup (tile width),
+  * block_barriers -- wavefront-local or workgroup-wide lane exchanges,
+with HIP events on the launch stream, and returns the fastest.  Results are
+cached in a JSON file keyed by the problem so a process tunes once.
+"""
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import cb
+
+ROWS = (4, 6, 8, 12, 16)
+LINES = (0, 1, 2, 4, 8, 16, 32, 64)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "cb_tune.json")
+
+
+def _key(bands, n, precision, shape, axis, fused):
+    return "r%d|n%d|%s|%s|ax%d|%s|%s" % ((len(bands) - 1) // 2, n, precision, "x".join(map(str, shape)), axis,
+                                        "fused" if fused else "solve", ",".join("%.17g" % b for b in bands))
+
+
+def candidates(bands, n, precision):
+    out = []
+    for rpl in ROWS:
+        try:
+            p = cb.Plan(bands, n, precision=precision, rows_per_lane=rpl, host_only=True)
+        except cb.CbError:
+            continue
+        L = p.info()["lanes"]
+        p.close()
+        for w in LINES:
+            if w and w * L > 1024:
+                continue
+            for bb in (0, 1):
+                out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb))
+    return out
+
+
+def _time(fn, reps, stream):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps=5, cache=DEFAULT_CACHE,
+         max_candidates=None):
+    """Return (best_kwargs, table) for solving/deriving along `axis` of tensor f."""
+    key = _key(bands, n, precision, tuple(f.shape), axis, stencil is not None)
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+        except (OSError, ValueError):
+            db = {}
+    if key in db:
+        return db[key]["best"], db[key]["table"]
+    stream = torch.cuda.current_stream()
+    out = torch.empty_like(f)
+    table = []
+    cands = candidates(bands, n, precision)
+    if max_candidates:
+        cands = cands[:max_candidates]
+    for c in cands:
+        try:
+            p = cb.Plan(bands, n, precision=precision, refine_iters=refine_iters, **c)
+        except cb.CbError:
+            continue
+        if stencil is not None:
+            fn = lambda: cb.apply_derivative(p, stencil, f, axis, out=out, stream=stream)
+        else:
+            fn = lambda: cb.solve(p, f, axis, out=out, stream=stream)
+        try:
+            ms = _time(fn, reps, stream)
+        except cb.CbError:
+            p.close()
+            continue
+        table.append(dict(c, ms=ms))
+        p.close()
+    best = min(table, key=lambda r: r["ms"])
+    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers")}
+    if cache:
+        db[key] = {"best": best, "table": table}
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        tmp = cache + ".tmp%d" % os.getpid()
+        json.dump(db, open(tmp, "w"), indent=1)
+        os.replace(tmp, cache)
+    return best, table
+
+
+def tuned_plan(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, **kw):
+    best, _ = tune(bands, n, f, axis, stencil, precision, refine_iters, **kw)
+    return cb.Plan(bands, n, precision=precision, refine_iters=refine_iters, **best)

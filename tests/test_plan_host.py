@@ -132,3 +132,15 @@ def test_bad_descriptors():
         cb.Plan([1 / 3, 1, 1 / 3], 2, host_only=True)
     with pytest.raises(cb.CbError):
         cb.Plan([1 / 3, 1, 1 / 3], 64, rows_per_lane=5, host_only=True)
+
+
+def test_tuner_candidates_are_valid_layouts():
+    from paper_2101_02286_amd import tune
+    c = tune.candidates([1 / 3, 1.0, 1 / 3], 512, "fp64")
+    rpls = {x["rows_per_lane"] for x in c}
+    assert rpls == {8, 16, 4}  # 512 = 64 x 8 = 32 x 16 = 128 x 4 (6 and 12 do not divide into 2^k lanes)
+    for x in c:
+        L = 512 // x["rows_per_lane"]
+        assert x["lines_per_wg"] * L <= 1024
+    c5 = tune.candidates([1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20], 613, "fp32_refine")
+    assert {x["rows_per_lane"] for x in c5} == {8, 16}  # ragged lines use the general layouts
