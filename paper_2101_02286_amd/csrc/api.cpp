@@ -239,13 +239,17 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
 }
 
 // --------------------------------------------------------- P > 1 launch --
-cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, hipStream_t stream) {
+cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
+                    hipStream_t stream) {
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
-  const WgKernel *k = find_wg_kernel(p.R, p.M, mode);
+  const int Q = st ? 3 : 0;
+  const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
   const int L = p.L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   NT = std::min(std::max(NT, L), 1024);
+  // keep the LDS of phase C (lane exchange + reduced-system state) within 64 KB
+  while (NT > L && ((size_t)NT * 2 * std::max(p.R, Q) + (size_t)2 * (NT / L) * p.P * p.R) * 8 > 65536) NT /= 2;
   const int W = NT / L;
   WgArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -256,6 +260,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.su = g.su;
   a.sv = g.sv;
   a.rs = g.rs;
+  a.n = g.n;
+  if (st) stencil_q(st, a.stc);
   a.lgL = ilog2(L);
   a.lgW = ilog2(W);
   a.P = p.P;
@@ -279,7 +285,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int64_t tiles = (g.nlines + W - 1) / W;
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
-  const size_t lds_a = (size_t)NT * 2 * p.R * sizeof(double);
+  const size_t lds_a = (size_t)NT * 2 * std::max(p.R, Q) * sizeof(double);
   const size_t lds_c = lds_a + (size_t)2 * W * p.P * p.R * sizeof(double);
   e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
@@ -385,7 +391,7 @@ cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const doub
   if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
   if (plan->p.precision != CB_FP64)
     return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
-  return launch_wg(plan->p, g, b, x, static_cast<hipStream_t>(stream));
+  return launch_wg(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
 }
 
 cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid, int32_t axis,
@@ -399,7 +405,11 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
   if (!f || !out) return fail(CB_ERR_INVALID_ARG, "f and out must be non-NULL");
   if (overlap(f, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and out overlap");
   if (!plan->p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "the fused stencil needs a cyclic plan");
-  if (plan->p.P != 1) return fail(CB_ERR_UNSUPPORTED, "fused stencil with P > 1 partitions");
+  if (plan->p.P != 1) {
+    if (plan->p.precision != CB_FP64)
+      return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
+    return launch_wg(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
+  }
   return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
 }
 

@@ -215,7 +215,7 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
   base = lu * a.su + lv * a.sv;
 }
 
-template <int R, int M, int MODE>
+template <int R, int M, int MODE, int Q>
 __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
                                                   int &start, int &m) {
@@ -223,33 +223,77 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   start = sg.lane_start[p.l];
   m = sg.lane_start[p.l + 1] - start;
   const int type = sg.lane_type[p.l];
-  const int64_t row0 = a.wg_start[part] + R + start;
+  const int64_t seg0 = a.wg_start[part] + R;  // first row of the interior block D_i
+  const int64_t row0 = seg0 + start;
   const double *in = a.in + base + row0 * a.rs;
 #pragma unroll
   for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
+  if (Q > 0) {  // fused stencil; the halo at the block's ends comes from global memory
+    constexpr int QQ = Q > 0 ? Q : 1;
+    double fp[QQ], fn[QQ];
+    halo<QQ, M>(v, m, false, p, xc, fp, fn);
+    if (p.l == 0) {
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int64_t r = seg0 - QQ + i;
+        r = r < 0 ? r + a.n : r;
+        fp[i] = active ? a.in[base + r * a.rs] : 0.0;
+      }
+    }
+    if (p.l == p.L - 1) {
+      const int64_t end = a.wg_start[part + 1];
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int64_t r = end + i;
+        r = r >= a.n ? r - a.n : r;
+        fn[i] = active ? a.in[base + r * a.rs] : 0.0;
+      }
+    }
+    double bb[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = -QQ; q <= QQ; ++q) acc += a.stc[q + 3] * row_at<QQ, M>(v, fp, fn, k + q, m, false);
+      bb[k] = k < m ? acc : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = bb[k];
+  }
   solve_segment<R, M, double, false>(v, sg, p, type, m, xc);
 }
 
-template <int R, int M, int MODE>
+template <int R, int M, int MODE, int Q>
 __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   extern __shared__ double smem[];
   LanePos p;
   int64_t line, base;
   bool active;
   wg_setup<R, M, MODE>(a, p, line, active, base);
-  Xchg xc{smem, R, (int)blockDim.x, 0, true};
+  Xchg xc{smem, (Q > R ? Q : R), (int)blockDim.x, 0, true};
   const int part = blockIdx.y;
   double v[M];
   int start, m;
-  wg_solve_interior<R, M, MODE>(a, p, active, base, part, xc, v, start, m);
+  wg_solve_interior<R, M, MODE, Q>(a, p, active, base, part, xc, v, start, m);
   if (!active) return;
   double *sc = a.scratch + (line * a.P + part) * 3 * R;
   if (p.l == 0) {
     const int64_t g0 = a.wg_start[part];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
-      sc[c] = a.in[base + (g0 + c) * a.rs];  // b~_i
-      sc[R + c] = v[c];                      // first R rows of y_i
+      double bt;
+      if (Q > 0) {  // stencil at the partition's interface row g0 + c
+        bt = 0.0;
+        for (int q = -3; q <= 3; ++q) {
+          int64_t r = g0 + c + q;
+          r = r < 0 ? r + a.n : (r >= a.n ? r - a.n : r);
+          bt += a.stc[q + 3] * a.in[base + r * a.rs];
+        }
+      } else {
+        bt = a.in[base + (g0 + c) * a.rs];
+      }
+      sc[c] = bt;         // b~_i
+      sc[R + c] = v[c];   // first R rows of y_i
     }
   }
   if (p.l == p.L - 1) {
@@ -259,9 +303,10 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   }
 }
 
-template <int R, int M, int MODE>
+template <int R, int M, int MODE, int Q>
 __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
   extern __shared__ double smem[];
+  constexpr int RS = Q > R ? Q : R;
   LanePos p;
   int64_t line, base;
   bool active;
@@ -269,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
   const int P = a.P, part = blockIdx.y, NT = blockDim.x;
   // reduced-system state in LDS: two buffers of [W][P][R], after the lane
   // exchange area
-  double *xr0 = smem + (size_t)NT * 2 * R;
+  double *xr0 = smem + (size_t)NT * 2 * RS;
   double *xr1 = xr0 + (size_t)p.W * P * R;
   const int64_t tile0 = (int64_t)blockIdx.x * p.W;
   for (int idx = p.tid; idx < p.W * P; idx += NT) {
@@ -331,10 +376,10 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
     xi[r] = cur[(p.li * P + part) * R + r];
     xi1[r] = cur[(p.li * P + (part + 1) % P) * R + r];
   }
-  Xchg xc{smem, R, NT, 0, true};
+  Xchg xc{smem, RS, NT, 0, true};
   double v[M];
   int start, m;
-  wg_solve_interior<R, M, MODE>(a, p, active, base, part, xc, v, start, m);
+  wg_solve_interior<R, M, MODE, Q>(a, p, active, base, part, xc, v, start, m);
   if (!active) return;
   const int64_t row0 = a.wg_start[part] + R + start;
   double *out = a.out + base + row0 * a.rs;
@@ -401,15 +446,17 @@ const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni) 
   return nullptr;
 }
 
-#define CB_WG_INST(R, M, MODE) {R, M, MODE, (const void *)&k_wg_a<R, M, MODE>, (const void *)&k_wg_c<R, M, MODE>}
+#define CB_WG_INST(R, M, MODE, Q) \
+  {R, M, MODE, Q, (const void *)&k_wg_a<R, M, MODE, Q>, (const void *)&k_wg_c<R, M, MODE, Q>}
+#define CB_WG_Q(R, M, MODE) CB_WG_INST(R, M, MODE, 0), CB_WG_INST(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {
-    CB_WG_INST(1, 8, MODE_X), CB_WG_INST(1, 8, MODE_S), CB_WG_INST(2, 8, MODE_X), CB_WG_INST(2, 8, MODE_S),
-    CB_WG_INST(1, 16, MODE_X), CB_WG_INST(1, 16, MODE_S), CB_WG_INST(2, 16, MODE_X), CB_WG_INST(2, 16, MODE_S),
+    CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),
+    CB_WG_Q(1, 16, MODE_X), CB_WG_Q(1, 16, MODE_S), CB_WG_Q(2, 16, MODE_X), CB_WG_Q(2, 16, MODE_S),
 };
 
-const WgKernel *find_wg_kernel(int R, int M, int mode) {
+const WgKernel *find_wg_kernel(int R, int M, int mode, int Q) {
   for (const auto &k : kWgKernels)
-    if (k.R == R && k.M == M && k.mode == mode) return &k;
+    if (k.R == R && k.M == M && k.mode == mode && k.Q == Q) return &k;
   return nullptr;
 }
 

@@ -24,7 +24,8 @@ struct WgArgs {
   const double *in;
   double *out;
   double *scratch;           // [nlines][P][3R]
-  int64_t nlines, nu, su, sv, rs;
+  int64_t nlines, nu, su, sv, rs, n;
+  double stc[7];             // fused stencil q = -3..3 (Q > 0 kernels)
   int lgL, lgW, P, nphase;
   const SegDev *segs;        // [P]
   const int *wg_start;       // [P+1]
@@ -49,7 +50,7 @@ struct LineKernel {
   const void *fn;
 };
 struct WgKernel {
-  int R, M, mode;
+  int R, M, mode, Q;
   const void *fn_a, *fn_c;
 };
 
@@ -74,7 +75,7 @@ constexpr int kBatchThreads = 512;
 
 const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
 const void *find_batch_kernel(int R, int M, int fp32);
-const WgKernel *find_wg_kernel(int R, int M, int mode);
+const WgKernel *find_wg_kernel(int R, int M, int mode, int Q);
 const void *stencil_kernel();
 
 }  // namespace cb

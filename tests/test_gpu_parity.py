@@ -192,3 +192,71 @@ def test_errors_leave_output_untouched(gpu):
     host = cb.Plan(TRI, 16, host_only=True)
     with pytest.raises(cb.CbError):
         cb.solve(host, b, 0, out=out)
+
+
+# ------------------------------------------------ full sizes, sampled lines --
+def sample_lines(arr, axis, picks):
+    """Lines (k, n) of a (nz, ny, nx) array along `axis` at (u, v) picks."""
+    if axis == 0:
+        return np.stack([arr[v, u, :] for u, v in picks])
+    if axis == 1:
+        return np.stack([arr[v, :, u] for u, v in picks])
+    return np.stack([arr[:, v, u] for u, v in picks])
+
+
+def sampled_check(f, out, axis, bands, lo, c, count=48, seed=0):
+    nz, ny, nx = f.shape
+    du, dv = [(ny, nz), (nx, nz), (nx, ny)][axis]
+    rng = np.random.default_rng(seed)
+    picks = [(int(rng.integers(du)), int(rng.integers(dv))) for _ in range(count)]
+    picks += [(0, 0), (du - 1, dv - 1)]  # first and last line
+    fl = sample_lines(f, axis, picks)[None]  # (1, k, n): lines along x
+    ref = oracle.apply_axis(fl, 0, bands, lo, c)[0]
+    got = sample_lines(out, axis, picks)
+    return relerr(got, ref)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_headline_512_full_size_sampled(gpu, axis):
+    """The benchmark's launch configuration on the full 512^3 grid."""
+    n = 512
+    f, _ = synth.random_modes((n, n, n), seed=0, device=gpu)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis)
+    torch.cuda.synchronize()
+    assert sampled_check(f.cpu().numpy(), out.cpu().numpy(), axis, TRI, lo, c) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_c2_256_full_size_sampled(gpu, axis):
+    n = 256
+    f, _ = synth.random_modes((n, n, n), seed=2, device=gpu)
+    fh = f.cpu().numpy()
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis).cpu().numpy()
+    assert sampled_check(fh, out, axis, TRI, lo, c) <= 1e-12
+    lo, c = schemes.stencil_interp_c2s(schemes.INTERP6)
+    out = cb.apply_derivative(cb.Plan(INTERP, n), cb.Stencil(lo, c), f, axis).cpu().numpy()
+    assert sampled_check(fh, out, axis, INTERP, lo, c) <= 1e-12
+
+
+def test_c3b_512_penta_z_full_size_sampled(gpu):
+    n = 512
+    f, _ = synth.random_modes((n, n, n), seed=1, device=gpu)
+    lo, c = deriv_stencil(schemes.DERIV10, n)
+    out = cb.apply_derivative(cb.Plan(PENTA, n), cb.Stencil(lo, c), f, 2)
+    torch.cuda.synchronize()
+    assert sampled_check(f.cpu().numpy(), out.cpu().numpy(), 2, PENTA, lo, c) <= 1e-12
+
+
+@pytest.mark.parametrize("P", [4, 7])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_partitioned_fused_derivative(gpu, P, axis):
+    n = 96 * P
+    shape = shape_with(axis, n, other=(5, 6))
+    f, _ = synth.random_modes(shape, seed=P + axis)
+    lo, c = deriv_stencil(schemes.DERIV10, n)
+    plan = cb.Plan(PENTA, n, partitions=P)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), axis, PENTA, lo, c)
+    assert relerr(out, ref) <= 1e-12
