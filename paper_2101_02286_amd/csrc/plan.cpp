@@ -164,20 +164,53 @@ cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR
       int e = 0;
       for (int q = Em; q >= 1; --q) os[e++] = -(2 * q - 1);
       for (int q = 1; q <= Ep; ++q) os[e++] = 2 * q - 1;
-      double a[16], x[4];
+      // Deep levels couple rows 2s apart; in a banded inverse those
+      // couplings decay geometrically, so an outer equation (column j+-3s)
+      // can vanish entirely.  Such an equation is vacuous: the outer row it
+      // pairs with (q = +-2) is then not needed and gets k = 0, exactly as at
+      // the ends of D.  Remaining equations are scaled to unit row maximum.
+      bool vac[4] = {false, false, false, false}, drop[4] = {false, false, false, false};
       for (int r = 0; r < m; ++r) {
-        x[r] = at(j, os[r]);
-        for (int u = 0; u < m; ++u) a[r * m + u] = at(j + qs[u] * s, os[r] - qs[u]);
+        double rmax = 0.0;
+        for (int u = 0; u < m; ++u) rmax = std::max(rmax, std::fabs(at(j + qs[u] * s, os[r] - qs[u])));
+        vac[r] = !(rmax > 1e-300) && at(j, os[r]) == 0.0 && std::abs(os[r]) > 1;
+        if (vac[r]) {
+          const int qd = os[r] < 0 ? -(1 - os[r]) / 2 : (os[r] + 1) / 2;
+          for (int u = 0; u < m; ++u)
+            if (qs[u] == qd) drop[u] = true;
+        }
       }
-      if (m > 0 && !small_solve(m, a, x, scale)) {
+      int qk[4], ok[4], mk = 0, ne = 0;
+      for (int r = 0; r < m; ++r)
+        if (!vac[r]) ok[ne++] = os[r];
+      for (int u = 0; u < m; ++u)
+        if (!drop[u]) qk[mk++] = qs[u];
+      if (ne != mk) {
         msg = "generalized PCR reduction system is singular";
         return CB_ERR_SINGULAR;
       }
-      for (int u = 0; u < m; ++u) g.k[((size_t)t * N + j) * 2 * R + kidx(qs[u], R)] = x[u];
+      double a[16], x[4];
+      for (int r = 0; r < mk; ++r) {
+        double rmax = 0.0;
+        for (int u = 0; u < mk; ++u) {
+          a[r * mk + u] = at(j + qk[u] * s, ok[r] - qk[u]);
+          rmax = std::max(rmax, std::fabs(a[r * mk + u]));
+        }
+        x[r] = at(j, ok[r]);
+        if (rmax > 0.0) {
+          for (int u = 0; u < mk; ++u) a[r * mk + u] /= rmax;
+          x[r] /= rmax;
+        }
+      }
+      if (mk > 0 && !small_solve(mk, a, x, 1.0)) {
+        msg = "generalized PCR reduction system is singular";
+        return CB_ERR_SINGULAR;
+      }
+      for (int u = 0; u < mk; ++u) g.k[((size_t)t * N + j) * 2 * R + kidx(qk[u], R)] = x[u];
       // the new row keeps the even multiples of s: offsets 2*o2*s, o2 in [-R, R]
       for (int o2 = -R; o2 <= R; ++o2) {
         double v = at(j, 2 * o2);
-        for (int u = 0; u < m; ++u) v -= x[u] * at(j + qs[u] * s, 2 * o2 - qs[u]);
+        for (int u = 0; u < mk; ++u) v -= x[u] * at(j + qk[u] * s, 2 * o2 - qk[u]);
         // offsets that leave D are structurally zero
         const int col = j + 2 * o2 * s;
         cn[j * W + o2 + R] = (col >= 0 && col < N) ? v : 0.0;

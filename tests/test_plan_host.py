@@ -144,3 +144,15 @@ def test_tuner_candidates_are_valid_layouts():
         assert x["lines_per_wg"] * L <= 1024
     c5 = tune.candidates([1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20], 613, "fp32_refine")
     assert {x["rows_per_lane"] for x in c5} == {8, 16}  # ragged lines use the general layouts
+
+
+def test_deep_levels_with_decayed_couplings():
+    """Penta interior blocks of 510 rows: at deep generalized-PCR levels the
+    couplings 2s apart decay to ~1e-37 and below; the factorisation must stay
+    exact (equilibrated Eq. (6) systems, vacuous outer equations)."""
+    n, P = 8192, 16
+    bands = _bands("penta")
+    p = cb.Plan(bands, n, partitions=P, host_only=True)
+    b = np.random.default_rng(2).standard_normal((1, n))
+    ref = oracle.solve_lines(b, bands)
+    assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
