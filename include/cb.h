@@ -182,6 +182,8 @@ typedef struct {
   int32_t red_pcr_steps;   /* block-PCR steps in it (Sec. 4 step counts) */
   int32_t red_detach_steps;/* detach (= reattach) steps in it */
   int64_t device_bytes;    /* device memory held by the plan */
+  int32_t rows_per_lane_strided; /* layout used by strided launches (P = 1); */
+  int32_t lanes_strided;         /* equal to the above when one layout serves both */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 
@@ -191,8 +193,10 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_t *len);
 
 /* Copy one host-side array of a plan (FP64 values; integer arrays are
- * converted) for inspection by tests.  `seg` selects the segment (0 for a
- * one-partition plan, else the workgroup partition).  which:
+ * converted) for inspection by tests.  `seg` selects the segment: for a
+ * one-partition plan 0 is the lane layout of unit-stride launches and 1 (when
+ * lanes_strided differs) that of strided launches; for P > 1 the workgroup
+ * partition.  which:
  *   0 lane coefficient blocks [ntypes][block] (layout: k[Tint][N][2r],
  *     dinv[N], Lt[r][r], Ut[r][r], S[N][r], Rm[N][r], N = M - r)
  *   1 lane block-PCR multipliers [Tred][L][2][r][r] (MU then ML)

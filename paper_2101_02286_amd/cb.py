@@ -52,7 +52,9 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in
                 ("r", "n", "cyclic", "precision", "refine_iters", "partitions", "lanes", "rows_per_lane",
                  "uniform", "interior_levels", "lane_levels", "red_phases", "red_pcr_steps",
-                 "red_detach_steps")] + [("device_bytes", ctypes.c_int64)]
+                 "red_detach_steps")] + [("device_bytes", ctypes.c_int64),
+                                         ("rows_per_lane_strided", ctypes.c_int32),
+                                         ("lanes_strided", ctypes.c_int32)]
 
 
 def lib():

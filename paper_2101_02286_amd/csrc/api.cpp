@@ -183,9 +183,11 @@ cb_status check_stencil(const cb_stencil *st) {
 // --------------------------------------------------------- P = 1 launch --
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                       hipStream_t stream) {
-  const SegPlan &sp = p.segs[0];
+  const int si = g.rs == 1 ? 0 : p.seg_s;  // lane layout for this launch's row stride
+  const SegPlan &sp = p.segs[si];
   const bool uni = sp.uniform != 0;
-  const int Q = st ? 3 : 0;
+  const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;
+  if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
   const bool fp32 = p.precision != CB_FP64;
   // MODE_X needs unit row stride; the vectorised uniform path also needs
   // 16-byte aligned line starts.
@@ -207,7 +209,11 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   } else {
     W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
+  // LDS: two exchange regions of max(2Q, 2r) doubles per thread, at most 64 KB
+  const int RS = std::max(2 * Q, 2 * p.R);
+  while (W > 1 && (size_t)W * L * 2 * RS * sizeof(double) > 65536) W /= 2;
   const int NT = W * L;
+  if ((size_t)NT * 2 * RS * sizeof(double) > 65536) return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup");
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
   // one wavefront and its exchanges need no workgroup barrier
   const bool wave_local = mode == MODE_X && L <= 64 && (64 % L == 0) && p.desc.block_barriers == 0;
@@ -220,15 +226,15 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   a.su = g.su;
   a.sv = g.sv;
   a.rs = g.rs;
+  a.nudiv = make_divmagic((uint32_t)g.nu);
   a.lgL = ilog2(L);
   a.lgW = ilog2(W);
   a.block_sync = wave_local ? 0 : 1;
   a.refine_iters = p.refine_iters;
-  a.seg = p.segdev_host[0];
+  a.seg = p.segdev_host[si];
   if (st) stencil_q(st, a.stc);
   for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
   a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
-  const int RS = std::max(Q, p.R);
   const size_t lds = (size_t)NT * 2 * RS * sizeof(double);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
@@ -243,13 +249,15 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
                     hipStream_t stream) {
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
   const int Q = st ? 3 : 0;
+  if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
   const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
   const int L = p.L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   NT = std::min(std::max(NT, L), 1024);
   // keep the LDS of phase C (lane exchange + reduced-system state) within 64 KB
-  while (NT > L && ((size_t)NT * 2 * std::max(p.R, Q) + (size_t)2 * (NT / L) * p.P * p.R) * 8 > 65536) NT /= 2;
+  const int RSw = 2 * std::max(p.R, Q);
+  while (NT > L && ((size_t)NT * 2 * RSw + (size_t)2 * (NT / L) * p.P * p.R) * 8 > 65536) NT /= 2;
   const int W = NT / L;
   WgArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -261,6 +269,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.sv = g.sv;
   a.rs = g.rs;
   a.n = g.n;
+  a.nudiv = make_divmagic((uint32_t)g.nu);
   if (st) stencil_q(st, a.stc);
   a.lgL = ilog2(L);
   a.lgW = ilog2(W);
@@ -285,7 +294,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int64_t tiles = (g.nlines + W - 1) / W;
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
-  const size_t lds_a = (size_t)NT * 2 * std::max(p.R, Q) * sizeof(double);
+  const size_t lds_a = (size_t)NT * 2 * RSw * sizeof(double);
   const size_t lds_c = lds_a + (size_t)2 * W * p.P * p.R * sizeof(double);
   e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
@@ -454,6 +463,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     const int L = p.L;
     if (L > kBatchThreads) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: line needs too many lanes");
     const int W = kBatchThreads / L;
+    if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: more than 2^31 lines");
     BatchItemDev &d = tab[i];
     std::memset(&d, 0, sizeof(d));
     LineArgs &a = d.a;
@@ -464,6 +474,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.su = g.su;
     a.sv = g.sv;
     a.rs = g.rs;
+    a.nudiv = make_divmagic((uint32_t)g.nu);
     a.lgL = ilog2(L);
     a.lgW = ilog2(W);
     a.block_sync = 1;
@@ -512,7 +523,7 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = (size_t)kBatchThreads * 2 * 3 * sizeof(double);
+  const size_t lds = (size_t)kBatchThreads * 2 * 6 * sizeof(double);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
   int ctas = std::max(1, ncu * std::max(per_cu, 1));
@@ -551,6 +562,8 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->red_pcr_steps = p.prog.pcr_steps;
   info->red_detach_steps = p.prog.detach_steps;
   info->device_bytes = p.dev_bytes;
+  info->rows_per_lane_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].M;
+  info->lanes_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].L;
   return CB_OK;
 }
 

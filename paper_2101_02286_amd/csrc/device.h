@@ -210,30 +210,44 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
 
 // Halo exchange of the Q rows on each side of the lane (periodic through the
 // lanes of a cyclic segment): prev[i] = row start-Q+i, next[i] = row start+m+i.
+// One exchange: each lane publishes its first Q and last Q rows.
 template <int Q, int M, typename V>
 __device__ __forceinline__ void halo(const V (&v)[M], int m, bool full, const LanePos &p, Xchg &xc,
                                      V (&prev)[Q], V (&next)[Q]) {
-  V out[Q];
+  V out[2 * Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
+    out[i] = v[i];
     if (full) {
-      out[i] = v[M - Q + i];
+      out[Q + i] = v[M - Q + i];
     } else {
       V r = (V)0;
 #pragma unroll
       for (int j = 0; j < M; ++j) r = (j == m - Q + i) ? v[j] : r;
-      out[i] = r;
+      out[Q + i] = r;
     }
   }
   xc.publish(p.tid, out);
-  xc.fetch(p.tid_of((p.l - 1) & (p.L - 1)), prev);
-  xc.done();
+  const double *pp = xc.slot(p.tid_of((p.l - 1) & (p.L - 1)));
+  const double *pn = xc.slot(p.tid_of((p.l + 1) & (p.L - 1)));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[i] = v[i];
-  xc.publish(p.tid, out);
-  xc.fetch(p.tid_of((p.l + 1) & (p.L - 1)), next);
+  for (int i = 0; i < Q; ++i) {
+    prev[i] = (V)pp[Q + i];
+    next[i] = (V)pn[i];
+  }
   xc.done();
 }
+
+// Unsigned 32-bit division by a runtime-invariant divisor d with a
+// host-precomputed multiplier (round-up method): q = (t + ((n - t) >> s1)) >> s2,
+// t = mulhi(mul, n).
+struct FastDiv {
+  uint32_t d, mul, s1, s2;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    const uint32_t t = __umulhi(mul, n);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
 
 // Value of row (k + q) relative to the lane start, from registers or halos.
 template <int Q, int M, typename V>

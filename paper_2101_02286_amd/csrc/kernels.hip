@@ -20,7 +20,7 @@ namespace cb {
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, int MODE, int Q, bool UNI>
 __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, double *smem) {
-  constexpr int RS = (Q > R ? Q : R);
+  constexpr int RS = (2 * Q > 2 * R ? 2 * Q : 2 * R);
   LanePos p;
   p.tid = threadIdx.x;
   p.lgL = a.lgL;
@@ -39,8 +39,10 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   const SegDev &sg = a.seg;
   const int64_t line = tile * p.W + p.li;
   const bool active = line < a.nlines;
-  const int64_t lu = active ? line % a.nu : 0, lv = active ? line / a.nu : 0;
-  const int64_t base = lu * a.su + lv * a.sv;
+  const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
+  const uint32_t line32 = active ? (uint32_t)line : 0u;
+  const uint32_t lv = fd.div(line32), lu = line32 - lv * a.nudiv.d;
+  const int64_t base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
   int start, m, type = 0;
   if (UNI) {
     m = M;
@@ -54,15 +56,23 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   const double *in = a.in + base + start * rs;
   double *out = a.out + base + start * rs;
 
+  // MODE_X: a lane's rows are one contiguous 8M-byte run, so one vector load
+  // instruction touches many cache lines partially; these loads go through
+  // the caches (a streaming hint would drop the lines between the partial
+  // accesses).  MODE_S: every row access is a whole 128-byte segment per 16
+  // lines, read once, so the loads are marked streaming.
   double b64[M];
   if (MODE == MODE_X && UNI && (M % 2 == 0)) {
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
 #pragma unroll
     for (int k = 0; k < M / 2; ++k) {
-      dbl2 t = active ? __builtin_nontemporal_load(in2 + k) : dbl2{0.0, 0.0};
+      dbl2 t = active ? in2[k] : dbl2{0.0, 0.0};
       b64[2 * k] = t.x;
       b64[2 * k + 1] = t.y;
     }
+  } else if (MODE == MODE_X) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? in[k] : 0.0;
   } else {
 #pragma unroll
     for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? __builtin_nontemporal_load(in + k * rs) : 0.0;
@@ -125,7 +135,11 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   if (MODE == MODE_X && UNI && (M % 2 == 0)) {
     dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
 #pragma unroll
-    for (int k = 0; k < M / 2; ++k) __builtin_nontemporal_store(dbl2{x64[2 * k], x64[2 * k + 1]}, out2 + k);
+    for (int k = 0; k < M / 2; ++k) out2[k] = dbl2{x64[2 * k], x64[2 * k + 1]};
+  } else if (MODE == MODE_X) {
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (UNI || k < m) out[k] = x64[k];
   } else {
 #pragma unroll
     for (int k = 0; k < M; ++k)
@@ -211,8 +225,10 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
   }
   line = (int64_t)blockIdx.x * p.W + p.li;
   active = line < a.nlines;
-  const int64_t lu = active ? line % a.nu : 0, lv = active ? line / a.nu : 0;
-  base = lu * a.su + lv * a.sv;
+  const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
+  const uint32_t line32 = active ? (uint32_t)line : 0u;
+  const uint32_t lv = fd.div(line32), lu = line32 - lv * a.nudiv.d;
+  base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
 }
 
 template <int R, int M, int MODE, int Q>
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   int64_t line, base;
   bool active;
   wg_setup<R, M, MODE>(a, p, line, active, base);
-  Xchg xc{smem, (Q > R ? Q : R), (int)blockDim.x, 0, true};
+  Xchg xc{smem, (Q > R ? 2 * Q : 2 * R), (int)blockDim.x, 0, true};
   const int part = blockIdx.y;
   double v[M];
   int start, m;
@@ -306,7 +322,7 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
 template <int R, int M, int MODE, int Q>
 __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
   extern __shared__ double smem[];
-  constexpr int RS = Q > R ? Q : R;
+  constexpr int RS = Q > R ? 2 * Q : 2 * R;
   LanePos p;
   int64_t line, base;
   bool active;
@@ -430,7 +446,8 @@ __global__ __launch_bounds__(256) void k_stencil(const StencilArgs a) {
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI) \
   {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, (const void *)&k_line<R, M, T, MODE, Q, UNI>}
 
-#define CB_LINE_Q(R, M, T, MODE, UNI) CB_LINE_INST(R, M, T, MODE, 0, UNI), CB_LINE_INST(R, M, T, MODE, 3, UNI)
+#define CB_LINE_Q(R, M, T, MODE, UNI) \
+  CB_LINE_INST(R, M, T, MODE, 0, UNI), CB_LINE_INST(R, M, T, MODE, 2, UNI), CB_LINE_INST(R, M, T, MODE, 3, UNI)
 #define CB_LINE_MODE(R, M, T, UNI) CB_LINE_Q(R, M, T, MODE_X, UNI), CB_LINE_Q(R, M, T, MODE_S, UNI)
 #define CB_LINE_T(R, M, UNI) CB_LINE_MODE(R, M, double, UNI), CB_LINE_MODE(R, M, float, UNI)
 #define CB_LINE_R(M, UNI) CB_LINE_T(1, M, UNI), CB_LINE_T(2, M, UNI)

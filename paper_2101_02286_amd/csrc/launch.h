@@ -9,10 +9,26 @@ namespace cb {
 // Row layout of a launch: unit-stride lines (MODE_X) or strided lines (MODE_S).
 enum { MODE_X = 0, MODE_S = 1 };
 
+// Magic numbers for dividing a 32-bit line index by nu (see FastDiv in device.h).
+struct DivMagic {
+  uint32_t d, mul, s1, s2;
+};
+inline DivMagic make_divmagic(uint32_t d) {
+  uint32_t l = 0;
+  while (l < 32 && (uint64_t(1) << l) < d) ++l;
+  DivMagic m;
+  m.d = d;
+  m.mul = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+  m.s1 = l > 0 ? 1 : 0;
+  m.s2 = l > 0 ? l - 1 : 0;
+  return m;
+}
+
 struct LineArgs {
   const double *in;
   double *out;
   int64_t nlines, nu, su, sv, rs;
+  DivMagic nudiv;            // line -> (u, v) = (line % nu, line / nu)
   int lgL, lgW, block_sync, refine_iters;
   SegDev seg;
   double stc[7];             // stencil coefficients for q = -3..3 (zero padded)
@@ -25,6 +41,7 @@ struct WgArgs {
   double *out;
   double *scratch;           // [nlines][P][3R]
   int64_t nlines, nu, su, sv, rs, n;
+  DivMagic nudiv;
   double stc[7];             // fused stencil q = -3..3 (Q > 0 kernels)
   int lgL, lgW, P, nphase;
   const SegDev *segs;        // [P]

@@ -537,16 +537,26 @@ cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
 }
 
 // ---------------------------------------------------- segment (lane level) --
+// Lane layout preferences.  Unit-stride launches read a lane's rows as one
+// contiguous run, so fewer rows per lane spread each load instruction over
+// fewer cache lines; strided launches read whole 128-byte row segments and
+// prefer more rows per lane (fewer lanes, fewer block-PCR levels in LDS).
+enum { PREF_X = 0, PREF_S = 1 };
+
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
-                 bool allow_uniform, int L_req = 0) {
-  static const int kUniM[] = {8, 16, 12, 6, 4};
+                 bool allow_uniform, int L_req = 0, int pref = PREF_S) {
+  static const int kUniMx[] = {4, 8, 6, 12, 16};
+  static const int kUniMs[] = {16, 12, 8, 6, 4};
+  const int *kUniM = pref == PREF_X ? kUniMx : kUniMs;
   if (allow_uniform) {
     for (int pass = 0; pass < 2; ++pass)
-      for (int m : kUniM) {
+      for (int mi = 0; mi < 5; ++mi) {
+        const int m = kUniM[mi];
         if (M_req && m != M_req) continue;
         if (m < 2 * R || S % m) continue;
         const int l = S / m;
-        if (!is_pow2(l) || l > (pass == 0 ? 64 : 1024)) continue;
+        const int lmax = pass == 0 ? (pref == PREF_X ? 256 : 64) : 1024;
+        if (!is_pow2(l) || l > lmax) continue;
         L = l;
         M = m;
         uniform = true;
@@ -571,10 +581,10 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
 
 cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
                         const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
-                        std::string &msg, int L_req = 0) {
+                        std::string &msg, int L_req = 0, int pref = PREF_S) {
   int L, M, m_uni;
   bool uni;
-  if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req)) {
+  if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req, pref)) {
     msg = "no lane layout for this segment length (rows_per_lane unsupported?)";
     return CB_ERR_UNSUPPORTED;
   }
@@ -707,9 +717,20 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   auto line_coef = [&](int g, int o) -> double { return p.bands[(size_t)g * W + o + R]; };
 
   if (P == 1) {
+    // segs[0]: layout for unit-stride launches; segs[seg_s]: for strided ones
     p.segs.resize(1);
-    cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg);
+    cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X);
     if (s != CB_OK) return s;
+    p.seg_s = 0;
+    if (!d.rows_per_lane) {
+      SegPlan alt;
+      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S);
+      if (s != CB_OK) return s;
+      if (alt.M != p.segs[0].M || alt.L != p.segs[0].L) {
+        p.segs.push_back(std::move(alt));
+        p.seg_s = 1;
+      }
+    }
     p.M = p.segs[0].M;
     p.L = p.segs[0].L;
     p.wg_start = {0, n};

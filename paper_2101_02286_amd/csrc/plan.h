@@ -88,8 +88,11 @@ struct Plan {
   int R = 1, n = 0, P = 1, M = 8, L = 1;
   int precision = CB_FP64, refine_iters = 0;
   int host_only = 0;
-  // segments: P == 1 -> segs[0] is the whole line; else segs[i] = D_i
+  // segments: P == 1 -> segs[0] is the whole line laid out for unit-stride
+  // launches and segs[seg_s] for strided launches (the same when seg_s = 0);
+  // P > 1 -> segs[i] = D_i of workgroup partition i
   std::vector<SegPlan> segs;
+  int seg_s = 0;
   // workgroup level (P > 1)
   std::vector<int> wg_start;           // P+1
   std::vector<double> SRg;             // per partition: S^G [N_i][R] then R^G [N_i][R]

@@ -23,16 +23,28 @@ def _offsets(R, M, T):
 def solve_segment(plan, b, seg=0):
     """b: (lines, S) -> x = D_seg^{-1} b by the lane scheme (cyclic or acyclic per plan)."""
     info = plan.info()
-    R, M, L = info["r"], info["rows_per_lane"], info["lanes"]
-    N = M - R
+    R = info["r"]
     types = plan.array(3, seg).astype(int)
     starts = plan.array(4, seg).astype(int)
     L = len(types)
+    flat = plan.array(0, seg)
+    ntypes = int(types.max()) + 1
+    M = None
+    for cand in range(2 * R, 33):  # the block size fixes the register slots M
+        Nc = cand - R
+        Tc = 0
+        while (1 << Tc) < Nc:
+            Tc += 1
+        if _offsets(R, cand, Tc)["end"] * ntypes == flat.size:
+            M = cand
+            break
+    assert M is not None
+    N = M - R
     T = 0
     while (1 << T) < N:
         T += 1
     o = _offsets(R, M, T)
-    coef = plan.array(0, seg).reshape(-1, o["end"])
+    coef = flat.reshape(-1, o["end"])
     Tred = 0
     while (1 << Tred) < L:
         Tred += 1
@@ -88,12 +100,13 @@ def solve_segment(plan, b, seg=0):
     return x
 
 
-def solve(plan, b):
-    """x = A^{-1} b for (lines, n) b, following the plan's decomposition."""
+def solve(plan, b, seg=0):
+    """x = A^{-1} b for (lines, n) b, following the plan's decomposition
+    (seg = 1 selects the strided-launch lane layout of a one-partition plan)."""
     info = plan.info()
     P, R = info["partitions"], info["r"]
     if P == 1:
-        return solve_segment(plan, b, 0)
+        return solve_segment(plan, b, seg)
     ws = plan.array(7).astype(int)
     SR = plan.array(5)
     LtUt = plan.array(6).reshape(P, 2, R, R)

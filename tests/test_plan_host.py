@@ -156,3 +156,18 @@ def test_deep_levels_with_decayed_couplings():
     b = np.random.default_rng(2).standard_normal((1, n))
     ref = oracle.solve_lines(b, bands)
     assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("n", [64, 256, 512, 1024])
+def test_strided_layout_reproduces_oracle(name, n):
+    """One-partition plans carry a second lane layout for strided launches."""
+    bands = _bands(name)
+    p = cb.Plan(bands, n, host_only=True)
+    info = p.info()
+    b = np.random.default_rng(n).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands)
+    for seg in ((0, 1) if info["lanes_strided"] != info["lanes"] else (0,)):
+        assert np.abs(plan_emulator.solve(p, b, seg) - ref).max() <= 1e-12 * np.abs(ref).max()
+    if n == 512:
+        assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (4, 16)
