@@ -49,7 +49,10 @@ template <> __device__ __forceinline__ const float *wf_of<float>(const SegDev &s
 // of RS doubles; exchange number k writes region k&1, waits at a barrier, and
 // reads partners' region k&1.  Exchange k+2 reuses the region only after the
 // barrier of exchange k+1, which every thread reaches after its reads of
-// exchange k, so one barrier per exchange suffices.
+// exchange k, so one barrier per exchange suffices.  Value i of thread t in
+// region r lives at base[(r * RS + i) * NT + t]: consecutive threads touch
+// consecutive words, so writes and (shifted) partner reads are free of bank
+// conflicts.
 struct Xchg {
   double *base;  // LDS, NT * 2 * RS doubles
   int RS;        // doubles per region
@@ -67,19 +70,20 @@ struct Xchg {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  __device__ __forceinline__ double *slot(int tid) { return base + ((size_t)tid * 2 + (k & 1)) * RS; }
+  // value i of thread tid in the current region is slot(tid)[i * NT]
+  __device__ __forceinline__ double *slot(int tid) { return base + (size_t)(k & 1) * RS * NT + tid; }
   template <int CNT, typename V>
   __device__ __forceinline__ void publish(int tid, const V (&vals)[CNT]) {
     double *p = slot(tid);
 #pragma unroll
-    for (int i = 0; i < CNT; ++i) p[i] = (double)vals[i];
+    for (int i = 0; i < CNT; ++i) p[(size_t)i * NT] = (double)vals[i];
     sync();
   }
   template <int CNT, typename V>
   __device__ __forceinline__ void fetch(int tid_src, V (&out)[CNT]) {
     const double *p = slot(tid_src);
 #pragma unroll
-    for (int i = 0; i < CNT; ++i) out[i] = (V)p[i];
+    for (int i = 0; i < CNT; ++i) out[i] = (V)p[(size_t)i * NT];
   }
   __device__ __forceinline__ void done() { ++k; }
 };
@@ -232,8 +236,8 @@ __device__ __forceinline__ void halo(const V (&v)[M], int m, bool full, const La
   const double *pn = xc.slot(p.tid_of((p.l + 1) & (p.L - 1)));
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    prev[i] = (V)pp[Q + i];
-    next[i] = (V)pn[i];
+    prev[i] = (V)pp[(size_t)(Q + i) * xc.NT];
+    next[i] = (V)pn[(size_t)i * xc.NT];
   }
   xc.done();
 }

@@ -86,7 +86,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     for (int k = 0; k < M; ++k) {
       double acc = 0.0;
 #pragma unroll
-      for (int q = -Q; q <= Q; ++q) acc += a.stc[q + Q] * row_at<(Q > 0 ? Q : 1), M>(b64, fp, fn, k + q, m, UNI);
+      for (int q = -Q; q <= Q; ++q) acc += a.stc[q + 3] * row_at<(Q > 0 ? Q : 1), M>(b64, fp, fn, k + q, m, UNI);
       bb[k] = (UNI || k < m) ? acc : 0.0;
     }
 #pragma unroll
