@@ -197,8 +197,9 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
                     (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
     if (!al) mode = MODE_S;
   }
-  const void *fn = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni);
-  if (!fn) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
+  const LineKernel *lk = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni);
+  if (!lk) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
+  const void *fn = lk->fn;
   const int L = sp.L;
   if (L > 1024) return fail(CB_ERR_UNSUPPORTED, "line needs more than 1024 lanes");
   int W;
@@ -211,9 +212,10 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread, at most 64 KB
   const int RS = std::max(2 * Q, 2 * p.R);
-  while (W > 1 && (size_t)W * L * 2 * RS * sizeof(double) > 65536) W /= 2;
+  while (W > 1 && ((size_t)W * L * 2 * RS * sizeof(double) > 65536 || W * L > lk->max_threads)) W /= 2;
   const int NT = W * L;
-  if ((size_t)NT * 2 * RS * sizeof(double) > 65536) return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup");
+  if ((size_t)NT * 2 * RS * sizeof(double) > 65536 || NT > lk->max_threads)
+    return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup of this kernel");
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
   // one wavefront and its exchanges need no workgroup barrier
   const bool wave_local = mode == MODE_X && L <= 64 && (64 % L == 0) && p.desc.block_barriers == 0;

@@ -147,8 +147,16 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   }
 }
 
+// Workgroup size bound of a line-kernel instance: register-heavy instances
+// (FP32 reduction with FP64 refinement state, 12-16 rows per lane, or the
+// general lane layout) get up to 256 VGPRs by allowing at most 512 threads.
+template <int M, typename T, bool UNI>
+constexpr int line_max_threads() {
+  return (sizeof(T) == 4 || M >= 12 || !UNI) ? 512 : 1024;
+}
+
 template <int R, int M, typename T, int MODE, int Q, bool UNI>
-__global__ __launch_bounds__(1024) void k_line(const LineArgs a) {
+__global__ __launch_bounds__((line_max_threads<M, T, UNI>())) void k_line(const LineArgs a) {
   extern __shared__ double smem[];
   line_tile<R, M, T, MODE, Q, UNI>(a, (int64_t)blockIdx.x, smem);
 }
@@ -444,7 +452,8 @@ __global__ __launch_bounds__(256) void k_stencil(const StencilArgs a) {
 // Dispatch tables
 // ------------------------------------------------------------------------
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI) \
-  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, (const void *)&k_line<R, M, T, MODE, Q, UNI>}
+  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, line_max_threads<M, T, UNI>(), \
+   (const void *)&k_line<R, M, T, MODE, Q, UNI>}
 
 #define CB_LINE_Q(R, M, T, MODE, UNI) \
   CB_LINE_INST(R, M, T, MODE, 0, UNI), CB_LINE_INST(R, M, T, MODE, 2, UNI), CB_LINE_INST(R, M, T, MODE, 3, UNI)
@@ -457,9 +466,9 @@ static const LineKernel kLineKernels[] = {
     CB_LINE_R(8, false), CB_LINE_R(16, false),
 };
 
-const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni) {
+const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni) {
   for (const auto &k : kLineKernels)
-    if (k.R == R && k.M == M && k.fp32 == fp32 && k.mode == mode && k.Q == Q && k.uni == uni) return k.fn;
+    if (k.R == R && k.M == M && k.fp32 == fp32 && k.mode == mode && k.Q == Q && k.uni == uni) return &k;
   return nullptr;
 }
 

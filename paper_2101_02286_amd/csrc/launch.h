@@ -64,6 +64,7 @@ struct StencilArgs {
 struct LineKernel {
   int R, M, fp32, mode, Q;
   bool uni;
+  int max_threads;  // workgroup size bound of the instance
   const void *fn;
 };
 struct WgKernel {
@@ -90,7 +91,7 @@ struct BatchKernel {
 };
 constexpr int kBatchThreads = 512;
 
-const void *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
+const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
 const void *find_batch_kernel(int R, int M, int fp32);
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q);
 const void *stencil_kernel();

@@ -544,7 +544,7 @@ cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
 enum { PREF_X = 0, PREF_S = 1 };
 
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
-                 bool allow_uniform, int L_req = 0, int pref = PREF_S) {
+                 bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16) {
   static const int kUniMx[] = {4, 8, 6, 12, 16};
   static const int kUniMs[] = {16, 12, 8, 6, 4};
   const int *kUniM = pref == PREF_X ? kUniMx : kUniMs;
@@ -553,6 +553,7 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
       for (int mi = 0; mi < 5; ++mi) {
         const int m = kUniM[mi];
         if (M_req && m != M_req) continue;
+        if (!M_req && m > m_max) continue;
         if (m < 2 * R || S % m) continue;
         const int l = S / m;
         const int lmax = pass == 0 ? (pref == PREF_X ? 256 : 64) : 1024;
@@ -566,7 +567,7 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
   }
   uniform = false;
   m_uni = 0;
-  M = M_req ? M_req : ((S + 7) / 8 <= 64 ? 8 : 16);
+  M = M_req ? M_req : ((S + 7) / 8 <= 64 || m_max < 16 ? 8 : 16);
   if (M != 8 && M != 16) return false;
   if (L_req > 0) {
     L = L_req;
@@ -581,10 +582,11 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
 
 cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
                         const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
-                        std::string &msg, int L_req = 0, int pref = PREF_S) {
+                        std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16) {
   int L, M, m_uni;
   bool uni;
-  if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req, pref)) {
+  if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req, pref,
+                   m_max)) {
     msg = "no lane layout for this segment length (rows_per_lane unsupported?)";
     return CB_ERR_UNSUPPORTED;
   }
@@ -718,13 +720,17 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
 
   if (P == 1) {
     // segs[0]: layout for unit-stride launches; segs[seg_s]: for strided ones
+    // the FP32 reduction keeps FP64 refinement state beside it: at most 8 rows
+    // per lane unless asked for
+    const int m_max = d.precision == CB_FP64 ? 16 : 8;
     p.segs.resize(1);
-    cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X);
+    cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X,
+                                m_max);
     if (s != CB_OK) return s;
     p.seg_s = 0;
     if (!d.rows_per_lane) {
       SegPlan alt;
-      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S);
+      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max);
       if (s != CB_OK) return s;
       if (alt.M != p.segs[0].M || alt.L != p.segs[0].L) {
         p.segs.push_back(std::move(alt));
