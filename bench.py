@@ -72,7 +72,7 @@ def headline(args):
     bands, (a, b) = tri6()
     st = deriv_stencil(n, a, b)
     f, _ = synth.random_modes(shape, seed=0, device=dev)
-    if args.no_tune:
+    if not args.tune:  # the plans' automatic launch shape
         plans = [cb.Plan(bands, n)] * 3
         tuned = None
     else:  # autotuned launch shape per direction (rows per lane, lines per workgroup, barriers)
@@ -132,7 +132,7 @@ def headline(args):
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(f, bands, [st, st, st], seconds=args.cpu_seconds)
-    for p in plans:
+    for p in set(plans):
         p.close()
     return res
 
@@ -291,7 +291,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-tune", action="store_true", help="use the plans' automatic launch shape")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shape per direction first")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only (the multi-GPU split is a design, not part of this build)",

@@ -162,11 +162,12 @@ int64_t span_elems(const cb_grid *g) {
   return s;
 }
 
-bool overlap(const void *a, const void *b, int64_t elems) {
+// Do [a, a + ea) and [b, b + eb) (FP64 elements) intersect?
+bool overlap2(const void *a, int64_t ea, const void *b, int64_t eb) {
   const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
-  const int64_t bytes = elems * 8;
-  return pa < pb + bytes && pb < pa + bytes;
+  return pa < pb + eb * 8 && pb < pa + ea * 8;
 }
+bool overlap(const void *a, const void *b, int64_t elems) { return overlap2(a, elems, b, elems); }
 
 void stencil_q(const cb_stencil *st, double out[7]) {
   for (int i = 0; i < 7; ++i) out[i] = 0.0;
@@ -206,7 +207,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (p.desc.lines_per_wg > 0) {
     W = p.desc.lines_per_wg;
   } else if (mode == MODE_X) {
-    W = std::max(1, 256 / L);
+    W = std::max(1, 512 / L);  // 512-thread workgroups (measured best on 512^3)
   } else {
     W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
@@ -492,8 +493,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
   }
   for (int i = 0; i < n_items; ++i)
     for (int j = i + 1; j < n_items; ++j)
-      if (overlap(items[i].out, items[j].out,
-                  std::max(span_elems(&items[i].grid), span_elems(&items[j].grid))))
+      if (overlap2(items[i].out, span_elems(&items[i].grid), items[j].out, span_elems(&items[j].grid)))
         return fail(CB_ERR_INVALID_ARG, "cb_batch_build: outputs of two items overlap");
   std::vector<char> host(cb_batch_workspace_size(n_items), 0);
   BatchHdr h;
