@@ -88,6 +88,8 @@ typedef struct {
   int32_t block_barriers; /* 0: lane exchanges of a line that lies inside one
                              wavefront use wavefront-local ordering only;
                              1: always workgroup barriers */
+  int32_t x_staging;      /* unit-stride lines: 0 automatic (= 2), 1 lanes load
+                             their rows directly, 2 through a coalesced LDS tile */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +

@@ -25,7 +25,7 @@ thread_local std::string g_err;
 
 // kernel selection (r, rows_per_lane, fp32) of each built batch workspace
 std::mutex g_batch_mu;
-std::map<void *, std::array<int, 3>> g_batch_sel;
+std::map<void *, std::array<int, 4>> g_batch_sel;  // + LDS bytes of staged coefficients
 
 cb_status fail(cb_status s, const std::string &m) {
   g_err = m;
@@ -104,6 +104,7 @@ cb_status upload(Plan &p) {
     g.uniform = s.uniform;
     g.m = s.m_uniform;
     g.block = s.block;
+    g.ntypes = s.ntypes;
     g.lane_type = reinterpret_cast<const int *>(base + so[i].lt);
     g.lane_start = reinterpret_cast<const int *>(base + so[i].ls);
     g.coef64 = reinterpret_cast<const double *>(base + so[i].c64);
@@ -207,15 +208,29 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (p.desc.lines_per_wg > 0) {
     W = p.desc.lines_per_wg;
   } else if (mode == MODE_X) {
-    W = std::max(1, 512 / L);  // 512-thread workgroups (measured best on 512^3)
+    // staged unit-stride lines: one line per workgroup measured best (512^3);
+    // direct loads: 512-thread workgroups
+    W = (p.desc.x_staging != 1) ? 1 : std::max(1, 512 / L);
   } else {
     W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread, at most 64 KB
   const int RS = std::max(2 * Q, 2 * p.R);
-  while (W > 1 && ((size_t)W * L * 2 * RS * sizeof(double) > 65536 || W * L > lk->max_threads)) W /= 2;
+  // general layouts stage their coefficient blocks in LDS when they are small
+  const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp32 ? 4 : 8);
+  const bool coef_lds = !uni && coef_bytes <= 16384;
+  const size_t coef_dbl = coef_lds ? (coef_bytes + 7) / 8 : 0;
+  // unit-stride lines of general layouts (and, on request, uniform ones) are
+  // loaded and stored through an LDS tile of W lines
+  const int xs = p.desc.x_staging;
+  const bool stage_x = mode == MODE_X && xs != 1;
+  const int64_t pitch = stage_x ? g.n + g.n / sp.M + 1 : 0;
+  auto lds_of = [&](int w) {
+    return ((size_t)w * L * 2 * RS + coef_dbl + (size_t)w * pitch) * sizeof(double);
+  };
+  while (W > 1 && (lds_of(W) > 65536 || W * L > lk->max_threads)) W /= 2;
   const int NT = W * L;
-  if ((size_t)NT * 2 * RS * sizeof(double) > 65536 || NT > lk->max_threads)
+  if (lds_of(W) > 65536 || NT > lk->max_threads)
     return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup of this kernel");
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
   // one wavefront and its exchanges need no workgroup barrier
@@ -234,11 +249,16 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   a.lgW = ilog2(W);
   a.block_sync = wave_local ? 0 : 1;
   a.refine_iters = p.refine_iters;
+  a.coef_lds = coef_lds ? 1 : 0;
+  a.stage_x = stage_x ? 1 : 0;
+  a.n = (int)g.n;
+  a.stage_off = (int64_t)NT * 2 * RS + (int64_t)coef_dbl;
+  a.stage_pitch = pitch;
   a.seg = p.segdev_host[si];
   if (st) stencil_q(st, a.stc);
   for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
   a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
-  const size_t lds = (size_t)NT * 2 * RS * sizeof(double);
+  const size_t lds = lds_of(W);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
   void *args[] = {&a};
@@ -260,7 +280,11 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   NT = std::min(std::max(NT, L), 1024);
   // keep the LDS of phase C (lane exchange + reduced-system state) within 64 KB
   const int RSw = 2 * std::max(p.R, Q);
-  while (NT > L && ((size_t)NT * 2 * RSw + (size_t)2 * (NT / L) * p.P * p.R) * 8 > 65536) NT /= 2;
+  size_t coef_doubles = 0;
+  for (const SegPlan &sp : p.segs) coef_doubles = std::max(coef_doubles, (size_t)sp.ntypes * sp.block);
+  const bool coef_lds = coef_doubles * 8 <= 16384;
+  const size_t extra = coef_lds ? coef_doubles : 0;
+  while (NT > L && ((size_t)NT * 2 * RSw + (size_t)2 * (NT / L) * p.P * p.R + extra) * 8 > 65536) NT /= 2;
   const int W = NT / L;
   WgArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -278,8 +302,12 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.lgW = ilog2(W);
   a.P = p.P;
   a.nphase = p.prog.nphase;
+  a.coef_lds = coef_lds ? 1 : 0;
+  a.coef_off_a = (int64_t)NT * 2 * RSw;
+  a.coef_off_c = a.coef_off_a + (int64_t)2 * W * p.P * p.R;
   a.segs = p.segdev;
   a.wg_start = p.d_wg_start;
+  a.bands = p.d_bands;
   a.SR = p.d_SRg;
   a.SR_off = p.d_SRg_off;
   a.LtUt = p.d_LtUtg;
@@ -297,8 +325,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int64_t tiles = (g.nlines + W - 1) / W;
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
-  const size_t lds_a = (size_t)NT * 2 * RSw * sizeof(double);
-  const size_t lds_c = lds_a + (size_t)2 * W * p.P * p.R * sizeof(double);
+  const size_t lds_a = ((size_t)a.coef_off_a + extra) * sizeof(double);
+  const size_t lds_c = ((size_t)a.coef_off_c + extra) * sizeof(double);
   e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
   hipError_t e2 = hipFreeAsync(scratch, stream);
@@ -438,6 +466,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
   std::vector<BatchItemDev> tab(n_items);
   int R0 = -1, M0 = -1, fp0 = -1;
   int64_t tiles = 0;
+  size_t coef_max = 0;
   for (int i = 0; i < n_items; ++i) {
     const cb_batch_item &it = items[i];
     cb_status s = check_plan_for_solve(it.plan);
@@ -483,6 +512,12 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.block_sync = 1;
     a.refine_iters = p.refine_iters;
     a.seg = p.segdev_host[0];
+    {
+      const SegPlan &sp = p.segs[0];
+      const size_t cb = sp.uniform ? 0 : (size_t)sp.ntypes * sp.block * (fp ? 4 : 8);
+      a.coef_lds = (!sp.uniform && cb <= 16384) ? 1 : 0;
+      if (a.coef_lds) coef_max = std::max(coef_max, cb);
+    }
     if (it.stencil) stencil_q(it.stencil, a.stc);
     else a.stc[3] = 1.0;  // identity stencil: b = input
     for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
@@ -507,13 +542,13 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_build: copy");
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_batch_sel[workspace] = {R0, M0, fp0};
+  g_batch_sel[workspace] = {R0, M0, fp0, (int)coef_max};
   return CB_OK;
 }
 
 cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace is NULL");
-  std::array<int, 3> sel;
+  std::array<int, 4> sel;
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     auto itr = g_batch_sel.find(workspace);
@@ -525,7 +560,7 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = (size_t)kBatchThreads * 2 * 6 * sizeof(double);
+  const size_t lds = (size_t)kBatchThreads * 2 * 6 * sizeof(double) + (size_t)sel[3];
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
   int ctas = std::max(1, ncu * std::max(per_cu, 1));

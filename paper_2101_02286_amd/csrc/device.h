@@ -104,16 +104,37 @@ __device__ __forceinline__ T select_idx(const T (&y)[N], int idx) {
   return r;
 }
 
+// Where a lane's coefficient block is read from: the plan in global memory
+// through the constant address space (uniform plans: scalar loads), or a
+// copy staged in LDS (general plans, whose lanes read different blocks).
+enum { CSRC_GLOBAL = 0, CSRC_LDS = 1 };
+template <int CSRC, typename T>
+__device__ __forceinline__ T cget(const T *p) {
+  if (CSRC == CSRC_LDS) return *p;
+  return cld(p);
+}
+
+// Copy the plan's lane-type coefficient blocks into LDS (all threads take
+// part; ends with a workgroup barrier).
+template <typename T>
+__device__ __forceinline__ void stage_coef(const SegDev &sg, T *dst, int tid, int nt) {
+  const T *src = coef_of<T>(sg);
+  const int cnt = sg.ntypes * sg.block;
+  for (int i = tid; i < cnt; i += nt) dst[i] = src[i];
+  __syncthreads();
+}
+
 // Solve the segment in place: on entry v[0..m) holds b of the lane's rows, on
-// exit x.  Padding slots (k >= m) hold zero and stay zero.
-template <int R, int M, typename T, bool UNI>
+// exit x.  Padding slots (k >= m) hold zero and stay zero.  `cl` is the LDS
+// copy of the coefficient blocks when CSRC == CSRC_LDS.
+template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL>
 __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const LanePos &p, int type,
-                                              int m, Xchg &xc) {
+                                              int m, Xchg &xc, const T *cl = nullptr) {
   constexpr int N = M - R;
   constexpr int TI = ceil_log2_c(N);
   constexpr int RR = R * R;
   constexpr CoefOff off = coef_offsets(R, M, TI);
-  const T *cf = coef_of<T>(sg) + (size_t)(UNI ? 0 : type) * sg.block;
+  const T *cf = (CSRC == CSRC_LDS ? cl : coef_of<T>(sg)) + (size_t)(UNI ? 0 : type) * sg.block;
 
   // ---- interior generalized PCR, D_l y = b (Eq. (3) with stored k) ----
   T y[N];
@@ -129,8 +150,8 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
       const T *kj = cf + off.k + (t * N + j) * 2 * R;
 #pragma unroll
       for (int q = 1; q <= R; ++q) {
-        if (j - q * s >= 0) acc -= cld(kj + R - q) * y[j - q * s];
-        if (j + q * s < N) acc -= cld(kj + R + q - 1) * y[j + q * s];
+        if (j - q * s >= 0) acc -= cget<CSRC>(kj + R - q) * y[j - q * s];
+        if (j + q * s < N) acc -= cget<CSRC>(kj + R + q - 1) * y[j + q * s];
       }
       yn[j] = acc;
     }
@@ -138,7 +159,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     for (int j = 0; j < N; ++j) y[j] = yn[j];
   }
 #pragma unroll
-  for (int j = 0; j < N; ++j) y[j] *= cld(cf + off.dinv + j);
+  for (int j = 0; j < N; ++j) y[j] *= cget<CSRC>(cf + off.dinv + j);
 
   // ---- interface RHS b^_l = b~_l - L~_l y_{l-1} - U~_l y_l (Eq. (21)) ----
   const int nl = m - R;  // real interior rows of this lane
@@ -154,7 +175,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
   for (int a = 0; a < R; ++a) {
     T acc = v[a];
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc -= cld(cf + off.Lt + a * R + c) * yprev[c] + cld(cf + off.Ut + a * R + c) * y[c];
+    for (int c = 0; c < R; ++c) acc -= cget<CSRC>(cf + off.Lt + a * R + c) * yprev[c] + cget<CSRC>(cf + off.Ut + a * R + c) * y[c];
     xt[a] = acc;
   }
 
@@ -205,7 +226,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     T acc = y[j];
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      acc -= cld(cf + off.S + j * R + c) * xt[c] + cld(cf + off.Rm + j * R + c) * xnext[c];
+      acc -= cget<CSRC>(cf + off.S + j * R + c) * xt[c] + cget<CSRC>(cf + off.Rm + j * R + c) * xnext[c];
     v[R + j] = acc;
   }
 #pragma unroll

@@ -61,8 +61,34 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   // the caches (a streaming hint would drop the lines between the partial
   // accesses).  MODE_S: every row access is a whole 128-byte segment per 16
   // lines, read once, so the loads are marked streaming.
+  // Staged unit-stride path: the line's L lanes read it with consecutive
+  // 8-byte words (whole cache lines per instruction) into an LDS tile where
+  // one pad word follows every M words, so each lane's M contiguous rows are
+  // read back without bank conflicts.
+  double *tb = nullptr;
+  const bool staged = MODE == MODE_X && a.stage_x;
+  if (staged) tb = smem + a.stage_off + (size_t)p.li * a.stage_pitch;
   double b64[M];
-  if (MODE == MODE_X && UNI && (M % 2 == 0)) {
+  if (staged) {
+    const double *lin = a.in + base;
+    double t[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      t[k] = (active && e < a.n) ? __builtin_nontemporal_load(lin + e) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (e < a.n) tb[e + e / M] = t[k];
+    }
+    xc.sync();
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = start + k;
+      b64[k] = (UNI || k < m) ? tb[e + e / M] : 0.0;
+    }
+  } else if (MODE == MODE_X && UNI && (M % 2 == 0)) {
     const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
 #pragma unroll
     for (int k = 0; k < M / 2; ++k) {
@@ -93,12 +119,25 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     for (int k = 0; k < M; ++k) b64[k] = bb[k];
   }
 
+  // general layouts: the lanes read different coefficient blocks, staged in LDS
+  T *cl = nullptr;
+  if (!UNI && a.coef_lds) {
+    cl = reinterpret_cast<T *>(smem + (size_t)2 * RS * blockDim.x);
+    stage_coef<T>(sg, cl, p.tid, blockDim.x);
+  }
+  auto solve = [&](T(&v)[M]) {
+    if (!UNI && a.coef_lds)
+      solve_segment<R, M, T, UNI, CSRC_LDS>(v, sg, p, type, m, xc, cl);
+    else
+      solve_segment<R, M, T, UNI, CSRC_GLOBAL>(v, sg, p, type, m, xc);
+  };
+
   double x64[M];
   if (sizeof(T) == 8) {
     T v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
-    solve_segment<R, M, T, UNI>(v, sg, p, type, m, xc);
+    solve(v);
 #pragma unroll
     for (int k = 0; k < M; ++k) x64[k] = (double)v[k];
   } else {
@@ -125,12 +164,28 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
           }
         }
       }
-      solve_segment<R, M, T, UNI>(v, sg, p, type, m, xc);
+      solve(v);
 #pragma unroll
       for (int k = 0; k < M; ++k) x64[k] += (double)v[k];
     }
   }
 
+  if (staged) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = start + k;
+      if (UNI || k < m) tb[e + e / M] = x64[k];
+    }
+    xc.sync();
+    if (!active) return;
+    double *lout = a.out + base;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (e < a.n) __builtin_nontemporal_store(tb[e + e / M], lout + e);
+    }
+    return;
+  }
   if (!active) return;
   if (MODE == MODE_X && UNI && (M % 2 == 0)) {
     dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
@@ -239,11 +294,18 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
   base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
 }
 
-template <int R, int M, int MODE, int Q>
+// Solve the interior block D_i of workgroup partition `part` for the lane's
+// rows.  With xi/xi1 given (phase C), the right-hand side first loses the
+// couplings to the interface unknowns x~_i (first r rows of D_i) and
+// x~_{i+1} (last r rows), so the solve returns x_i = D_i^{-1}[b_i - L_i x~_i
+// - U_i x~_{i+1}] directly (Eq. (9)).
+template <int R, int M, int MODE, int Q, bool ADJ>
 __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
-                                                  int &start, int &m) {
+                                                  int &start, int &m, double *coef_lds,
+                                                  const double (&xi)[R], const double (&xi1)[R]) {
   const SegDev &sg = a.segs[part];
+  if (a.coef_lds) stage_coef<double>(sg, coef_lds, p.tid, blockDim.x);
   start = sg.lane_start[p.l];
   m = sg.lane_start[p.l + 1] - start;
   const int type = sg.lane_type[p.l];
@@ -284,7 +346,29 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = bb[k];
   }
-  solve_segment<R, M, double, false>(v, sg, p, type, m, xc);
+  if (ADJ) {
+    const int S = sg.S;
+    constexpr int W2 = 2 * R + 1;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int sr = start + k;  // row within D_i
+      if (k < m && (sr < R || sr >= S - R)) {
+        const double *bd = a.bands + (seg0 + sr) * W2;
+#pragma unroll
+        for (int o = -R; o <= R; ++o) {
+          const int t = sr + o;
+          // R <= 2: select among the interface values instead of indexing a
+          // register array with a runtime index
+          if (t < 0) v[k] -= bd[o + R] * (R + t == 0 ? xi[0] : xi[R - 1]);        // row R+t of x~_i
+          else if (t >= S) v[k] -= bd[o + R] * (t - S == 0 ? xi1[0] : xi1[R - 1]);  // row t-S of x~_{i+1}
+        }
+      }
+    }
+  }
+  if (a.coef_lds)
+    solve_segment<R, M, double, false, CSRC_LDS>(v, sg, p, type, m, xc, coef_lds);
+  else
+    solve_segment<R, M, double, false, CSRC_GLOBAL>(v, sg, p, type, m, xc);
 }
 
 template <int R, int M, int MODE, int Q>
@@ -298,7 +382,9 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   const int part = blockIdx.y;
   double v[M];
   int start, m;
-  wg_solve_interior<R, M, MODE, Q>(a, p, active, base, part, xc, v, start, m);
+  const double none[R] = {};
+  wg_solve_interior<R, M, MODE, Q, false>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a, none,
+                                          none);
   if (!active) return;
   double *sc = a.scratch + (line * a.P + part) * 3 * R;
   if (p.l == 0) {
@@ -403,23 +489,13 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
   Xchg xc{smem, RS, NT, 0, true};
   double v[M];
   int start, m;
-  wg_solve_interior<R, M, MODE, Q>(a, p, active, base, part, xc, v, start, m);
+  wg_solve_interior<R, M, MODE, Q, true>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c, xi, xi1);
   if (!active) return;
   const int64_t row0 = a.wg_start[part] + R + start;
   double *out = a.out + base + row0 * a.rs;
-  const double *sg = a.SR + a.SR_off[part];
-  const int Ni = a.wg_start[part + 1] - a.wg_start[part] - R;
-  const double *rg = sg + (size_t)Ni * R;
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    if (k < m) {
-      const int row = start + k;
-      double acc = v[k];
-#pragma unroll
-      for (int c = 0; c < R; ++c) acc -= sg[row * R + c] * xi[c] + rg[row * R + c] * xi1[c];
-      out[k * a.rs] = acc;
-    }
-  }
+  for (int k = 0; k < M; ++k)
+    if (k < m) out[k * a.rs] = v[k];
   if (p.l == 0) {
     const int64_t g0 = a.wg_start[part];
 #pragma unroll
@@ -433,11 +509,20 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
 __global__ __launch_bounds__(256) void k_stencil(const StencilArgs a) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= a.total) return;
-  // idx enumerates (v, j, u) with u fastest so threads run along x
-  const int64_t u = idx % a.nu;
-  const int64_t rest = idx / a.nu;
-  const int64_t j = rest % a.n;
-  const int64_t vv = rest / a.n;
+  // consecutive threads touch consecutive addresses: along the line when it
+  // is unit-stride (idx = (v, u, j)), else across lines (idx = (v, j, u))
+  int64_t u, j, vv;
+  if (a.rs == 1) {
+    j = idx % a.n;
+    const int64_t rest = idx / a.n;
+    u = rest % a.nu;
+    vv = rest / a.nu;
+  } else {
+    u = idx % a.nu;
+    const int64_t rest = idx / a.nu;
+    j = rest % a.n;
+    vv = rest / a.n;
+  }
   const int64_t base = u * a.su + vv * a.sv;
   double acc = 0.0;
   for (int q = a.lo; q <= a.hi; ++q) {

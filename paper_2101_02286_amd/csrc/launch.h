@@ -30,6 +30,11 @@ struct LineArgs {
   int64_t nlines, nu, su, sv, rs;
   DivMagic nudiv;            // line -> (u, v) = (line % nu, line / nu)
   int lgL, lgW, block_sync, refine_iters;
+  int coef_lds;              // general layout: coefficient blocks staged in LDS
+  int stage_x;               // unit-stride lines go through an LDS tile
+  int n;                     // line length
+  int64_t stage_off;         // LDS offset (doubles) of the tile
+  int64_t stage_pitch;       // doubles per line in the tile (n + n/M + 1)
   SegDev seg;
   double stc[7];             // stencil coefficients for q = -3..3 (zero padded)
   double bands[5];           // constant bands a_{-R..R} (refinement residual)
@@ -44,8 +49,11 @@ struct WgArgs {
   DivMagic nudiv;
   double stc[7];             // fused stencil q = -3..3 (Q > 0 kernels)
   int lgL, lgW, P, nphase;
+  int coef_lds;              // stage each partition's coefficient blocks in LDS
+  int64_t coef_off_a, coef_off_c;  // their LDS offsets (doubles) in phases A and C
   const SegDev *segs;        // [P]
   const int *wg_start;       // [P+1]
+  const double *bands;       // [n][2R+1] band rows of the line (Eq. (9) couplings)
   const double *SR;          // S^G, R^G per partition
   const int64_t *SR_off;     // [P]
   const double *LtUt;        // [P][2][R][R]

@@ -545,7 +545,7 @@ enum { PREF_X = 0, PREF_S = 1 };
 
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
                  bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16) {
-  static const int kUniMx[] = {4, 8, 6, 12, 16};
+  static const int kUniMx[] = {8, 4, 6, 12, 16};
   static const int kUniMs[] = {16, 12, 8, 6, 4};
   const int *kUniM = pref == PREF_X ? kUniMx : kUniMs;
   if (allow_uniform) {
@@ -556,7 +556,7 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
         if (!M_req && m > m_max) continue;
         if (m < 2 * R || S % m) continue;
         const int l = S / m;
-        const int lmax = pass == 0 ? (pref == PREF_X ? 256 : 64) : 1024;
+        const int lmax = pass == 0 ? 64 : 1024;
         if (!is_pow2(l) || l > lmax) continue;
         L = l;
         M = m;
@@ -674,8 +674,8 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     return CB_ERR_UNSUPPORTED;
   }
   if (d.lines_per_wg < 0 || d.lines_per_wg > 1024 || (d.lines_per_wg & (d.lines_per_wg - 1)) ||
-      d.block_barriers < 0 || d.block_barriers > 1) {
-    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1";
+      d.block_barriers < 0 || d.block_barriers > 1 || d.x_staging < 0 || d.x_staging > 2) {
+    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1; x_staging 0..2";
     return CB_ERR_INVALID_ARG;
   }
   const int R = d.r, n = d.n, W = 2 * R + 1;

@@ -76,7 +76,7 @@ struct RedProgram {
 
 // Device view of a segment plan (POD, passed inside kernel arguments).
 struct SegDev {
-  int S, L, M, Tint, Tred, uniform, m, block;
+  int S, L, M, Tint, Tred, uniform, m, block, ntypes;
   const int *lane_type, *lane_start;
   const double *coef64, *red64, *wf64;
   const float *coef32, *red32, *wf32;

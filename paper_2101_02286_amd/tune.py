@@ -6,6 +6,7 @@ For one (bands, n, precision, grid shape, axis) it times every valid choice of
     PCR across lanes, log2(lanes) levels),
   * lines_per_wg  -- lines per workgroup (tile width),
   * block_barriers -- wavefront-local or workgroup-wide lane exchanges,
+  * x_staging     -- unit-stride lines read directly or through an LDS tile,
 with HIP events on the launch stream, and returns the fastest.  Results are
 cached in a JSON file keyed by the problem so a process tunes once.
 """
@@ -40,7 +41,8 @@ def candidates(bands, n, precision):
             if w and w * L > 1024:
                 continue
             for bb in (0, 1):
-                out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb))
+                for xs in (1, 2):
+                    out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb, x_staging=xs))
     return out
 
 
@@ -93,7 +95,7 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
         table.append(dict(c, ms=ms))
         p.close()
     best = min(table, key=lambda r: r["ms"])
-    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers")}
+    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers", "x_staging")}
     if cache:
         db[key] = {"best": best, "table": table}
         os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -260,3 +260,16 @@ def test_partitioned_fused_derivative(gpu, P, axis):
     out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
     ref = oracle.apply_axis(f.numpy(), axis, PENTA, lo, c)
     assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [64, 500, 512, 613])
+@pytest.mark.parametrize("xs", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_unit_stride_staging_paths(gpu, n, xs, prec):
+    """Direct per-lane loads and the LDS-staged coalesced path give the same answer."""
+    f, _ = synth.random_modes((6, 5, n), seed=n + xs)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    plan = cb.Plan(TRI, n, x_staging=xs, precision=prec)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), 0).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), 0, TRI, lo, c)
+    assert relerr(out, ref) <= 1e-12

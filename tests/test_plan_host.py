@@ -170,4 +170,4 @@ def test_strided_layout_reproduces_oracle(name, n):
     for seg in ((0, 1) if info["lanes_strided"] != info["lanes"] else (0,)):
         assert np.abs(plan_emulator.solve(p, b, seg) - ref).max() <= 1e-12 * np.abs(ref).max()
     if n == 512:
-        assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (4, 16)
+        assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (8, 16)
