@@ -9,6 +9,23 @@
 
 namespace cb {
 
+// Workgroup size bound of a line-kernel instance: register-heavy instances
+// (FP32 reduction with FP64 refinement state, 12-16 rows per lane, or the
+// general lane layout) get up to 256 VGPRs by allowing at most 512 threads.
+template <int M, typename T, bool UNI>
+constexpr int line_max_threads() {
+  return (sizeof(T) == 4 || !UNI) ? 512 : 1024;
+}
+
+// Exchange region size (doubles per thread and region): halos of unit-stride
+// lines with direct loads go through the lane exchange (2Q values); strided
+// lines read their halo rows from global memory, so only the 2r-value
+// exchanges of the solve and the refinement residual remain.
+template <int R, int Q, int MODE>
+constexpr int line_region() {
+  return MODE == MODE_S ? 2 * R : (2 * Q > 2 * R ? 2 * Q : 2 * R);
+}
+
 // ------------------------------------------------------------------------
 // Line solver for one-partition lines (P = 1): load -> [stencil] -> solve
 // [-> FP64 residual refinement] -> store, all on chip.  One workgroup per
@@ -20,7 +37,7 @@ namespace cb {
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, int MODE, int Q, bool UNI>
 __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, double *smem) {
-  constexpr int RS = (2 * Q > 2 * R ? 2 * Q : 2 * R);
+  constexpr int RS = line_region<R, Q, MODE>();
   LanePos p;
   p.tid = threadIdx.x;
   p.lgL = a.lgL;
@@ -37,6 +54,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   }
   Xchg xc{smem, RS, (int)blockDim.x, 0, a.block_sync != 0};
   const SegDev &sg = a.seg;
+  const int nrow = sg.S;  // line length (the whole line is this plan's one segment)
   const int64_t line = tile * p.W + p.li;
   const bool active = line < a.nlines;
   const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
@@ -75,12 +93,12 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int e = p.l + k * p.L;
-      t[k] = (active && e < a.n) ? __builtin_nontemporal_load(lin + e) : 0.0;
+      t[k] = (active && e < nrow) ? __builtin_nontemporal_load(lin + e) : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int e = p.l + k * p.L;
-      if (e < a.n) tb[e + e / M] = t[k];
+      if (e < nrow) tb[e + e / M] = t[k];
     }
     xc.sync();
 #pragma unroll
@@ -105,8 +123,31 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   }
 
   if (Q > 0) {  // fused right-hand-side stencil (Eq. (1)/(2)), periodic
-    double fp[Q > 0 ? Q : 1], fn[Q > 0 ? Q : 1];
-    halo<(Q > 0 ? Q : 1), M>(b64, m, UNI, p, xc, fp, fn);
+    constexpr int QQ = Q > 0 ? Q : 1;
+    double fp[QQ], fn[QQ];
+    if (staged) {  // the neighbouring rows are in the LDS tile
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int e = start - QQ + i;
+        e = e < 0 ? e + nrow : e;
+        fp[i] = tb[e + e / M];
+        e = start + m + i;
+        e = e >= nrow ? e - nrow : e;
+        fn[i] = tb[e + e / M];
+      }
+    } else if (MODE == MODE_S) {  // reread them (other lanes' rows, in L2)
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int e = start - QQ + i;
+        e = e < 0 ? e + nrow : e;
+        fp[i] = active ? a.in[base + (int64_t)e * rs] : 0.0;
+        e = start + m + i;
+        e = e >= nrow ? e - nrow : e;
+        fn[i] = active ? a.in[base + (int64_t)e * rs] : 0.0;
+      }
+    } else {
+      halo<QQ, M>(b64, m, UNI, p, xc, fp, fn);
+    }
     double bb[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -182,7 +223,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int e = p.l + k * p.L;
-      if (e < a.n) __builtin_nontemporal_store(tb[e + e / M], lout + e);
+      if (e < nrow) __builtin_nontemporal_store(tb[e + e / M], lout + e);
     }
     return;
   }
@@ -200,14 +241,6 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     for (int k = 0; k < M; ++k)
       if (UNI || k < m) __builtin_nontemporal_store(x64[k], out + k * rs);
   }
-}
-
-// Workgroup size bound of a line-kernel instance: register-heavy instances
-// (FP32 reduction with FP64 refinement state, 12-16 rows per lane, or the
-// general lane layout) get up to 256 VGPRs by allowing at most 512 threads.
-template <int M, typename T, bool UNI>
-constexpr int line_max_threads() {
-  return (sizeof(T) == 4 || M >= 12 || !UNI) ? 512 : 1024;
 }
 
 template <int R, int M, typename T, int MODE, int Q, bool UNI>
