@@ -212,11 +212,11 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
     // direct loads: 512-thread workgroups
     W = (p.desc.x_staging != 1) ? 1 : std::max(1, 512 / L);
   } else {
-    W = std::max(1, std::min(32, 1024 / L));  // 32 adjacent lines: 256-byte row segments
+    W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread, at most 64 KB
   // exchange region size per thread (see line_region in kernels.hip)
-  const int RS = mode == MODE_S ? 2 * p.R : std::max(2 * Q, 2 * p.R);
+  const int RS = std::max(2 * Q, 2 * p.R);
   // general layouts stage their coefficient blocks in LDS when they are small
   const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp32 ? 4 : 8);
   const bool coef_lds = !uni && coef_bytes <= 16384;

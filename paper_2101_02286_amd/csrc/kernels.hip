@@ -17,13 +17,11 @@ constexpr int line_max_threads() {
   return (sizeof(T) == 4 || !UNI) ? 512 : 1024;
 }
 
-// Exchange region size (doubles per thread and region): halos of unit-stride
-// lines with direct loads go through the lane exchange (2Q values); strided
-// lines read their halo rows from global memory, so only the 2r-value
-// exchanges of the solve and the refinement residual remain.
+// Exchange region size (doubles per thread and region): the halo exchange
+// carries 2Q values, the refinement residual 2r.
 template <int R, int Q, int MODE>
 constexpr int line_region() {
-  return MODE == MODE_S ? 2 * R : (2 * Q > 2 * R ? 2 * Q : 2 * R);
+  return 2 * Q > 2 * R ? 2 * Q : 2 * R;
 }
 
 // ------------------------------------------------------------------------
@@ -134,16 +132,6 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
         e = start + m + i;
         e = e >= nrow ? e - nrow : e;
         fn[i] = tb[e + e / M];
-      }
-    } else if (MODE == MODE_S) {  // reread them (other lanes' rows, in L2)
-#pragma unroll
-      for (int i = 0; i < QQ; ++i) {
-        int e = start - QQ + i;
-        e = e < 0 ? e + nrow : e;
-        fp[i] = active ? a.in[base + (int64_t)e * rs] : 0.0;
-        e = start + m + i;
-        e = e >= nrow ? e - nrow : e;
-        fn[i] = active ? a.in[base + (int64_t)e * rs] : 0.0;
       }
     } else {
       halo<QQ, M>(b64, m, UNI, p, xc, fp, fn);
