@@ -90,6 +90,9 @@ typedef struct {
                              1: always workgroup barriers */
   int32_t x_staging;      /* unit-stride lines: 0 automatic (= 2), 1 lanes load
                              their rows directly, 2 through a coalesced LDS tile */
+  int32_t interior;       /* solve of each lane's interior block D_l: 0 automatic
+                             (= 1), 1 generalized PCR (Sec. 2), 2 banded
+                             elimination in registers (rows_per_lane 8/12/16) */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +
@@ -186,6 +189,7 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the plan */
   int32_t rows_per_lane_strided; /* layout used by strided launches (P = 1); */
   int32_t lanes_strided;         /* equal to the above when one layout serves both */
+  int32_t interior_elimination;  /* 1 when lane interiors use banded elimination */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 
@@ -199,8 +203,9 @@ cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_
  * one-partition plan 0 is the lane layout of unit-stride launches and 1 (when
  * lanes_strided differs) that of strided launches; for P > 1 the workgroup
  * partition.  which:
- *   0 lane coefficient blocks [ntypes][block] (layout: k[Tint][N][2r],
- *     dinv[N], Lt[r][r], Ut[r][r], S[N][r], Rm[N][r], N = M - r)
+ *   0 lane coefficient blocks [ntypes][block] (layout: k[Tint][N][2r] or,
+ *     with elimination, lu[N][2r]; then dinv[N], Lt[r][r], Ut[r][r],
+ *     S[N][r], Rm[N][r], N = M - r)
  *   1 lane block-PCR multipliers [Tred][L][2][r][r] (MU then ML)
  *   2 lane final blocks [L][r][r]
  *   3 lane types [L]          4 lane starts [L+1]

@@ -33,7 +33,7 @@ class PlanDesc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("lines_per_wg", ctypes.c_int32), ("block_barriers", ctypes.c_int32),
-                ("x_staging", ctypes.c_int32)]
+                ("x_staging", ctypes.c_int32), ("interior", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -55,7 +55,8 @@ class PlanInfo(ctypes.Structure):
                  "uniform", "interior_levels", "lane_levels", "red_phases", "red_pcr_steps",
                  "red_detach_steps")] + [("device_bytes", ctypes.c_int64),
                                          ("rows_per_lane_strided", ctypes.c_int32),
-                                         ("lanes_strided", ctypes.c_int32)]
+                                         ("lanes_strided", ctypes.c_int32),
+                                         ("interior_elimination", ctypes.c_int32)]
 
 
 def lib():
@@ -110,14 +111,14 @@ class Plan:
 
     def __init__(self, bands, n, cyclic=True, partitions=1, precision="fp64", refine_iters=0,
                  rows_per_lane=0, per_row=False, host_only=False, lines_per_wg=0, block_barriers=0,
-                 x_staging=0):
+                 x_staging=0, interior=0):
         import numpy as np
         b = np.ascontiguousarray(np.asarray(bands, dtype=np.float64))
         r = (b.shape[-1] - 1) // 2
         self._bands = b
         d = PlanDesc(r, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(per_row), int(cyclic),
                      int(partitions), PRECISIONS[precision], int(refine_iters), int(rows_per_lane),
-                     int(host_only), int(lines_per_wg), int(block_barriers), int(x_staging))
+                     int(host_only), int(lines_per_wg), int(block_barriers), int(x_staging), int(interior))
         h = ctypes.c_void_p()
         _check(lib().cb_plan(ctypes.byref(d), ctypes.byref(h)))
         self.h = h

@@ -105,6 +105,7 @@ cb_status upload(Plan &p) {
     g.m = s.m_uniform;
     g.block = s.block;
     g.ntypes = s.ntypes;
+    g.ilu = s.ilu;
     g.lane_type = reinterpret_cast<const int *>(base + so[i].lt);
     g.lane_start = reinterpret_cast<const int *>(base + so[i].ls);
     g.coef64 = reinterpret_cast<const double *>(base + so[i].c64);
@@ -199,7 +200,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
                     (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
     if (!al) mode = MODE_S;
   }
-  const LineKernel *lk = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni);
+  const LineKernel *lk = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni, sp.ilu != 0);
   if (!lk) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
   const void *fn = lk->fn;
   const int L = sp.L;
@@ -483,6 +484,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       return fail(CB_ERR_INVALID_ARG, "cb_batch_build: plans differ in r, rows_per_lane or precision");
     }
     if (p.M != 8 && p.M != 16) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: rows_per_lane must be 8 or 16");
+    if (p.segs[0].ilu) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: plans must use the PCR interior solve");
     Geo g;
     if ((s = geometry(&it.grid, it.axis, g))) return s;
     if (g.n != p.n) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: grid extent differs from plan n");
@@ -604,6 +606,7 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->device_bytes = p.dev_bytes;
   info->rows_per_lane_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].M;
   info->lanes_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].L;
+  info->interior_elimination = p.segs.empty() ? 0 : p.segs[0].ilu;
   return CB_OK;
 }
 

@@ -127,21 +127,37 @@ __device__ __forceinline__ void stage_coef(const SegDev &sg, T *dst, int tid, in
 // Solve the segment in place: on entry v[0..m) holds b of the lane's rows, on
 // exit x.  Padding slots (k >= m) hold zero and stay zero.  `cl` is the LDS
 // copy of the coefficient blocks when CSRC == CSRC_LDS.
-template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL>
+template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL, bool ILU = false>
 __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const LanePos &p, int type,
                                               int m, Xchg &xc, const T *cl = nullptr) {
   constexpr int N = M - R;
   constexpr int TI = ceil_log2_c(N);
   constexpr int RR = R * R;
-  constexpr CoefOff off = coef_offsets(R, M, TI);
+  constexpr CoefOff off = coef_offsets(R, M, TI, ILU);
   const T *cf = (CSRC == CSRC_LDS ? cl : coef_of<T>(sg)) + (size_t)(UNI ? 0 : type) * sg.block;
 
-  // ---- interior generalized PCR, D_l y = b (Eq. (3) with stored k) ----
   T y[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) y[j] = v[R + j];
+  if (ILU) {
+    // ---- interior by banded elimination in place, D_l = L U ----
 #pragma unroll
-  for (int t = 0; t < TI; ++t) {
+    for (int j = 1; j < N; ++j)
+#pragma unroll
+      for (int q = 1; q <= R; ++q)
+        if (j - q >= 0) y[j] -= cget<CSRC>(cf + off.k + j * 2 * R + q - 1) * y[j - q];
+#pragma unroll
+    for (int j = N - 1; j >= 0; --j) {
+      T acc = y[j] * cget<CSRC>(cf + off.dinv + j);
+#pragma unroll
+      for (int q = 1; q <= R; ++q)
+        if (j + q < N) acc -= cget<CSRC>(cf + off.k + j * 2 * R + R + q - 1) * y[j + q];
+      y[j] = acc;
+    }
+  }
+  // ---- interior generalized PCR, D_l y = b (Eq. (3) with stored k) ----
+#pragma unroll
+  for (int t = 0; t < (ILU ? 0 : TI); ++t) {
     const int s = 1 << t;
     T yn[N];
 #pragma unroll
@@ -158,8 +174,10 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
 #pragma unroll
     for (int j = 0; j < N; ++j) y[j] = yn[j];
   }
+  if (!ILU) {
 #pragma unroll
-  for (int j = 0; j < N; ++j) y[j] *= cget<CSRC>(cf + off.dinv + j);
+    for (int j = 0; j < N; ++j) y[j] *= cget<CSRC>(cf + off.dinv + j);
+  }
 
   // ---- interface RHS b^_l = b~_l - L~_l y_{l-1} - U~_l y_l (Eq. (21)) ----
   const int nl = m - R;  // real interior rows of this lane

@@ -71,7 +71,7 @@ struct StencilArgs {
 
 struct LineKernel {
   int R, M, fp32, mode, Q;
-  bool uni;
+  bool uni, ilu;
   int max_threads;  // workgroup size bound of the instance
   const void *fn;
 };
@@ -99,7 +99,7 @@ struct BatchKernel {
 };
 constexpr int kBatchThreads = 512;
 
-const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni);
+const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu);
 const void *find_batch_kernel(int R, int M, int fp32);
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q);
 const void *stencil_kernel();

@@ -1,0 +1,259 @@
+// Line-solver kernel template (one-partition lines) shared by the per-M
+// translation units lines_m*.hip and by the batched launch in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device.h"
+#include "launch.h"
+
+namespace cb {
+
+// Workgroup size bound of a line-kernel instance: register-heavy instances
+// (FP32 reduction with FP64 refinement state, 12-16 rows per lane, or the
+// general lane layout) get up to 256 VGPRs by allowing at most 512 threads.
+template <int M, typename T, bool UNI>
+constexpr int line_max_threads() {
+  return (sizeof(T) == 4 || !UNI) ? 512 : 1024;
+}
+
+// Exchange region size (doubles per thread and region): the halo exchange
+// carries 2Q values, the refinement residual 2r.
+template <int R, int Q, int MODE>
+constexpr int line_region() {
+  return 2 * Q > 2 * R ? 2 * Q : 2 * R;
+}
+
+// ------------------------------------------------------------------------
+// Line solver for one-partition lines (P = 1): load -> [stencil] -> solve
+// [-> FP64 residual refinement] -> store, all on chip.  One workgroup per
+// tile of W lines; the L lanes of a line hold its rows in registers.
+// MODE_X: rows of a line are contiguous (unit stride); a line's lanes are
+//         adjacent threads.  MODE_S: strided rows; threads of equal lane
+//         index cover W adjacent lines so each row access is one contiguous
+//         W*8-byte segment.
+// ------------------------------------------------------------------------
+template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU = false>
+__device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, double *smem) {
+  constexpr int RS = line_region<R, Q, MODE>();
+  LanePos p;
+  p.tid = threadIdx.x;
+  p.lgL = a.lgL;
+  p.lgW = a.lgW;
+  p.L = 1 << a.lgL;
+  p.W = 1 << a.lgW;
+  p.mode = MODE;
+  if (MODE == MODE_X) {
+    p.li = p.tid >> p.lgL;
+    p.l = p.tid & (p.L - 1);
+  } else {
+    p.l = p.tid >> p.lgW;
+    p.li = p.tid & (p.W - 1);
+  }
+  Xchg xc{smem, RS, (int)blockDim.x, 0, a.block_sync != 0};
+  const SegDev &sg = a.seg;
+  const int nrow = sg.S;  // line length (the whole line is this plan's one segment)
+  const int64_t line = tile * p.W + p.li;
+  const bool active = line < a.nlines;
+  const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
+  const uint32_t line32 = active ? (uint32_t)line : 0u;
+  const uint32_t lv = fd.div(line32), lu = line32 - lv * a.nudiv.d;
+  const int64_t base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
+  int start, m, type = 0;
+  if (UNI) {
+    m = M;
+    start = p.l * M;
+  } else {
+    start = sg.lane_start[p.l];
+    m = sg.lane_start[p.l + 1] - start;
+    type = sg.lane_type[p.l];
+  }
+  const int64_t rs = MODE == MODE_X ? 1 : a.rs;
+  const double *in = a.in + base + start * rs;
+  double *out = a.out + base + start * rs;
+
+  // MODE_X: a lane's rows are one contiguous 8M-byte run, so one vector load
+  // instruction touches many cache lines partially; these loads go through
+  // the caches (a streaming hint would drop the lines between the partial
+  // accesses).  MODE_S: every row access is a whole 128-byte segment per 16
+  // lines, read once, so the loads are marked streaming.
+  // Staged unit-stride path: the line's L lanes read it with consecutive
+  // 8-byte words (whole cache lines per instruction) into an LDS tile where
+  // one pad word follows every M words, so each lane's M contiguous rows are
+  // read back without bank conflicts.
+  double *tb = nullptr;
+  const bool staged = MODE == MODE_X && a.stage_x;
+  if (staged) tb = smem + a.stage_off + (size_t)p.li * a.stage_pitch;
+  double b64[M];
+  if (staged) {
+    const double *lin = a.in + base;
+    double t[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      t[k] = (active && e < nrow) ? __builtin_nontemporal_load(lin + e) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (e < nrow) tb[e + e / M] = t[k];
+    }
+    xc.sync();
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = start + k;
+      b64[k] = (UNI || k < m) ? tb[e + e / M] : 0.0;
+    }
+  } else if (MODE == MODE_X && UNI && (M % 2 == 0)) {
+    const dbl2 *in2 = reinterpret_cast<const dbl2 *>(in);
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) {
+      dbl2 t = active ? in2[k] : dbl2{0.0, 0.0};
+      b64[2 * k] = t.x;
+      b64[2 * k + 1] = t.y;
+    }
+  } else if (MODE == MODE_X) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? in[k] : 0.0;
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? __builtin_nontemporal_load(in + k * rs) : 0.0;
+  }
+
+  if (Q > 0) {  // fused right-hand-side stencil (Eq. (1)/(2)), periodic
+    constexpr int QQ = Q > 0 ? Q : 1;
+    double fp[QQ], fn[QQ];
+    if (staged) {  // the neighbouring rows are in the LDS tile
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int e = start - QQ + i;
+        e = e < 0 ? e + nrow : e;
+        fp[i] = tb[e + e / M];
+        e = start + m + i;
+        e = e >= nrow ? e - nrow : e;
+        fn[i] = tb[e + e / M];
+      }
+    } else {
+      halo<QQ, M>(b64, m, UNI, p, xc, fp, fn);
+    }
+    double bb[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = -Q; q <= Q; ++q) acc += a.stc[q + 3] * row_at<(Q > 0 ? Q : 1), M>(b64, fp, fn, k + q, m, UNI);
+      bb[k] = (UNI || k < m) ? acc : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) b64[k] = bb[k];
+  }
+
+  // general layouts: the lanes read different coefficient blocks, staged in LDS
+  T *cl = nullptr;
+  if (!UNI && a.coef_lds) {
+    cl = reinterpret_cast<T *>(smem + (size_t)2 * RS * blockDim.x);
+    stage_coef<T>(sg, cl, p.tid, blockDim.x);
+  }
+  auto solve = [&](T(&v)[M]) {
+    if (!UNI && a.coef_lds)
+      solve_segment<R, M, T, UNI, CSRC_LDS, ILU>(v, sg, p, type, m, xc, cl);
+    else
+      solve_segment<R, M, T, UNI, CSRC_GLOBAL, ILU>(v, sg, p, type, m, xc);
+  };
+
+  double x64[M];
+  if (sizeof(T) == 8) {
+    T v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
+    solve(v);
+#pragma unroll
+    for (int k = 0; k < M; ++k) x64[k] = (double)v[k];
+  } else {
+    // FP32 reduction with FP64 residual refinement: x <- x + A32^{-1}(b - A x)
+#pragma unroll
+    for (int k = 0; k < M; ++k) x64[k] = 0.0;
+    for (int it = 0; it <= a.refine_iters; ++it) {
+      T v[M];
+      if (it == 0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
+      } else {
+        double xp[R], xn[R];
+        halo<R, M>(x64, m, UNI, p, xc, xp, xn);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          v[k] = (T)0;
+          if (UNI || k < m) {  // padding slots (k >= m) have no row
+            double ax = 0.0;
+            const double *bd = a.bands_row ? a.bands_row + (int64_t)(start + k) * (2 * R + 1) : a.bands;
+#pragma unroll
+            for (int o = -R; o <= R; ++o) ax += bd[o + R] * row_at<R, M>(x64, xp, xn, k + o, m, UNI);
+            v[k] = (T)(b64[k] - ax);
+          }
+        }
+      }
+      solve(v);
+#pragma unroll
+      for (int k = 0; k < M; ++k) x64[k] += (double)v[k];
+    }
+  }
+
+  if (staged) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = start + k;
+      if (UNI || k < m) tb[e + e / M] = x64[k];
+    }
+    xc.sync();
+    if (!active) return;
+    double *lout = a.out + base;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (e < nrow) __builtin_nontemporal_store(tb[e + e / M], lout + e);
+    }
+    return;
+  }
+  if (!active) return;
+  if (MODE == MODE_X && UNI && (M % 2 == 0)) {
+    dbl2 *out2 = reinterpret_cast<dbl2 *>(out);
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) out2[k] = dbl2{x64[2 * k], x64[2 * k + 1]};
+  } else if (MODE == MODE_X) {
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (UNI || k < m) out[k] = x64[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (UNI || k < m) __builtin_nontemporal_store(x64[k], out + k * rs);
+  }
+}
+
+template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU>
+__global__ __launch_bounds__((line_max_threads<M, T, UNI>())) void k_line(const LineArgs a) {
+  extern __shared__ double smem[];
+  line_tile<R, M, T, MODE, Q, UNI, ILU>(a, (int64_t)blockIdx.x, smem);
+}
+
+
+#define CB_LINE_INST(R, M, T, MODE, Q, UNI, ILU) \
+  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<M, T, UNI>(), \
+   (const void *)&k_line<R, M, T, MODE, Q, UNI, ILU>}
+#define CB_LINE_Q(R, M, T, MODE, UNI, ILU)                                             \
+  CB_LINE_INST(R, M, T, MODE, 0, UNI, ILU), CB_LINE_INST(R, M, T, MODE, 2, UNI, ILU), \
+      CB_LINE_INST(R, M, T, MODE, 3, UNI, ILU)
+#define CB_LINE_MODE(R, M, T, UNI, ILU) CB_LINE_Q(R, M, T, MODE_X, UNI, ILU), CB_LINE_Q(R, M, T, MODE_S, UNI, ILU)
+#define CB_LINE_T(R, M, UNI, ILU) CB_LINE_MODE(R, M, double, UNI, ILU), CB_LINE_MODE(R, M, float, UNI, ILU)
+#define CB_LINE_R(M, UNI, ILU) CB_LINE_T(1, M, UNI, ILU), CB_LINE_T(2, M, UNI, ILU)
+
+// Per-M instance tables (defined in lines_m<M>.hip).
+const LineKernel *line_table_m4(int *count);
+const LineKernel *line_table_m6(int *count);
+const LineKernel *line_table_m8(int *count);
+const LineKernel *line_table_m12(int *count);
+const LineKernel *line_table_m16(int *count);
+
+}  // namespace cb

@@ -1,0 +1,14 @@
+// Line-kernel instances with 16 register rows per lane.
+#include "line.h"
+
+namespace cb {
+
+static const LineKernel kTable[] = {CB_LINE_R(16, true, false), CB_LINE_R(16, false, false), CB_LINE_R(16, true, true),
+                                    CB_LINE_R(16, false, true)};
+
+const LineKernel *line_table_m16(int *count) {
+  *count = (int)(sizeof(kTable) / sizeof(kTable[0]));
+  return kTable;
+}
+
+}  // namespace cb

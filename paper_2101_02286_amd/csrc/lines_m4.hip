@@ -1,0 +1,13 @@
+// Line-kernel instances with 4 register rows per lane.
+#include "line.h"
+
+namespace cb {
+
+static const LineKernel kTable[] = {CB_LINE_R(4, true, false)};
+
+const LineKernel *line_table_m4(int *count) {
+  *count = (int)(sizeof(kTable) / sizeof(kTable[0]));
+  return kTable;
+}
+
+}  // namespace cb

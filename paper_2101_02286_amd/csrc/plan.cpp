@@ -580,9 +580,39 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
   return true;
 }
 
+// Banded LU without pivoting of one lane's interior block (unit lower L):
+// out[j*2R + q-1] = L[j][j-q], out[j*2R + R+q-1] = U[j][j+q] / U[j][j],
+// dinv[j] = 1 / U[j][j].
+cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, double *dinv, std::string &msg) {
+  const int W = 2 * R + 1;
+  std::vector<double> a(band);
+  double scale = 0.0;
+  for (double v : band) scale = std::max(scale, std::fabs(v));
+  for (int k = 0; k < N; ++k) {
+    const double piv = a[k * W + R];
+    if (!(std::fabs(piv) > 1e-13 * scale)) {
+      msg = "interior elimination met a zero pivot";
+      return CB_ERR_SINGULAR;
+    }
+    for (int i = k + 1; i <= std::min(N - 1, k + R); ++i) {
+      const double l = a[i * W + (k - i + R)] / piv;
+      a[i * W + (k - i + R)] = l;
+      for (int j = k + 1; j <= std::min(N - 1, k + R); ++j) a[i * W + (j - i + R)] -= l * a[k * W + (j - k + R)];
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    dinv[j] = 1.0 / a[j * W + R];
+    for (int q = 1; q <= R; ++q) {
+      out[j * 2 * R + q - 1] = j - q >= 0 ? a[j * W + (R - q)] : 0.0;
+      out[j * 2 * R + R + q - 1] = j + q < N ? a[j * W + (R + q)] * dinv[j] : 0.0;
+    }
+  }
+  return CB_OK;
+}
+
 cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
                         const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
-                        std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16) {
+                        std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16, int interior = 0) {
   int L, M, m_uni;
   bool uni;
   if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req, pref,
@@ -600,6 +630,12 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   sp.Tred = ceil_log2(L);
   sp.uniform = uni;
   sp.m_uniform = m_uni;
+  // interior solve: 1 generalized PCR, 2 elimination; automatic = PCR
+  sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16)) ? 1 : 0;
+  if (interior == 2 && !sp.ilu) {
+    msg = "interior elimination needs rows_per_lane 8, 12 or 16";
+    return CB_ERR_UNSUPPORTED;
+  }
   std::vector<int> st(L + 1);
   const int base = S / L, extra = S % L;
   st[0] = 0;
@@ -609,8 +645,8 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   cb_status s = build_blocks(L, R, st, cyclic, coef, sp.Tint, B, msg);
   if (s != CB_OK) return s;
   // coefficient blocks, padded to N = M-R slots, deduplicated by content
-  const int blk = coef_block_size(R, M, sp.Tint);
-  const CoefOff off = coef_offsets(R, M, sp.Tint);
+  const int blk = coef_block_size(R, M, sp.Tint, sp.ilu);
+  const CoefOff off = coef_offsets(R, M, sp.Tint, sp.ilu);
   sp.block = blk;
   sp.lane_type.assign(L, 0);
   sp.coef.clear();
@@ -619,11 +655,26 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   for (int l = 0; l < L; ++l) {
     std::vector<double> b(blk, 0.0);
     const int Nl = st[l + 1] - st[l] - R;
-    for (int t = 0; t < sp.Tint; ++t)
+    if (sp.ilu) {
+      // the lane's interior band, rebuilt from the segment rows
+      std::vector<double> band((size_t)Nl * (2 * R + 1), 0.0);
       for (int j = 0; j < Nl; ++j)
-        for (int u = 0; u < 2 * R; ++u)
-          b[off.k + ((size_t)t * N + j) * 2 * R + u] = B.D[l].k[((size_t)t * Nl + j) * 2 * R + u];
-    for (int j = 0; j < Nl; ++j) b[off.dinv + j] = B.D[l].dinv[j];
+        for (int o = -R; o <= R; ++o)
+          if (j + o >= 0 && j + o < Nl) band[j * (2 * R + 1) + o + R] = coef(st[l] + R + j, o);
+      std::vector<double> lu((size_t)Nl * 2 * R), dv(Nl);
+      cb_status s2 = lane_lu(Nl, R, band, lu.data(), dv.data(), msg);
+      if (s2 != CB_OK) return s2;
+      for (int j = 0; j < Nl; ++j) {
+        for (int u = 0; u < 2 * R; ++u) b[off.k + j * 2 * R + u] = lu[j * 2 * R + u];
+        b[off.dinv + j] = dv[j];
+      }
+    } else {
+      for (int t = 0; t < sp.Tint; ++t)
+        for (int j = 0; j < Nl; ++j)
+          for (int u = 0; u < 2 * R; ++u)
+            b[off.k + ((size_t)t * N + j) * 2 * R + u] = B.D[l].k[((size_t)t * Nl + j) * 2 * R + u];
+      for (int j = 0; j < Nl; ++j) b[off.dinv + j] = B.D[l].dinv[j];
+    }
     for (int q = 0; q < R * R; ++q) {
       b[off.Lt + q] = B.Lt[l][q];
       b[off.Ut + q] = B.Ut[l][q];
@@ -674,8 +725,9 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     return CB_ERR_UNSUPPORTED;
   }
   if (d.lines_per_wg < 0 || d.lines_per_wg > 1024 || (d.lines_per_wg & (d.lines_per_wg - 1)) ||
-      d.block_barriers < 0 || d.block_barriers > 1 || d.x_staging < 0 || d.x_staging > 2) {
-    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1; x_staging 0..2";
+      d.block_barriers < 0 || d.block_barriers > 1 || d.x_staging < 0 || d.x_staging > 2 || d.interior < 0 ||
+      d.interior > 2) {
+    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1; x_staging and interior 0..2";
     return CB_ERR_INVALID_ARG;
   }
   const int R = d.r, n = d.n, W = 2 * R + 1;
@@ -725,12 +777,12 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     const int m_max = d.precision == CB_FP64 ? 16 : 8;
     p.segs.resize(1);
     cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X,
-                                m_max);
+                                m_max, d.interior);
     if (s != CB_OK) return s;
     p.seg_s = 0;
     if (!d.rows_per_lane) {
       SegPlan alt;
-      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max);
+      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, d.interior);
       if (s != CB_OK) return s;
       if (alt.M != p.segs[0].M || alt.L != p.segs[0].L) {
         p.segs.push_back(std::move(alt));
@@ -745,6 +797,10 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       return CB_ERR_INVALID_ARG;
     }
     return CB_OK;
+  }
+  if (d.interior == 2) {
+    msg = "interior elimination is available for one-partition plans";
+    return CB_ERR_UNSUPPORTED;
   }
   // P > 1: workgroup partitions, each with R interface rows and an interior
   // segment D_i solved by the lane-level scheme.
@@ -770,7 +826,7 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     const int g0 = p.wg_start[i] + R;
     const int S = p.wg_start[i + 1] - g0;
     auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
-    s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg);
+    s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg, PREF_S, 16, d.interior);
     if (s != CB_OK) return s;
   }
   p.M = M;

@@ -31,7 +31,7 @@ namespace cb {
 //   wf    [L][R][R]            (W + L^ + U^)^{-1} after the last level
 // ---------------------------------------------------------------------------
 struct SegPlan {
-  int S = 0, cyclic = 0, L = 0, M = 0, R = 0, N = 0, Tint = 0, Tred = 0;
+  int S = 0, cyclic = 0, L = 0, M = 0, R = 0, N = 0, Tint = 0, Tred = 0, ilu = 0;
   int uniform = 0, m_uniform = 0;
   int ntypes = 0, block = 0;
   std::vector<int> lane_type, lane_start;  // L, L+1
@@ -40,20 +40,26 @@ struct SegPlan {
   std::vector<double> wf;                  // L * R^2
 };
 
-constexpr int coef_block_size(int R, int M, int Tint) {
-  const int N = M - R;
-  return Tint * N * 2 * R + N + 2 * R * R + 2 * N * R;
+// Interior solve of a lane's block D_l: generalized PCR (k multipliers for
+// Tint levels) or, with `ilu`, banded elimination (D_l = L U, unit L):
+//   lu  [N][2R]  l_{j,q} = L[j][j-q] (index q-1), u'_{j,q} = U[j][j+q]/U[j][j]
+//                (index R+q-1); dinv = 1/U[j][j].
+constexpr int interior_size(int R, int M, int Tint, bool ilu) {
+  return ilu ? (M - R) * 2 * R : Tint * (M - R) * 2 * R;
+}
+constexpr int coef_block_size(int R, int M, int Tint, bool ilu = false) {
+  return interior_size(R, M, Tint, ilu) + (M - R) + 2 * R * R + 2 * (M - R) * R;
 }
 struct CoefOff {
   int k, dinv, Lt, Ut, S, Rm;
 };
-constexpr CoefOff coef_offsets(int R, int M, int Tint) {
+constexpr CoefOff coef_offsets(int R, int M, int Tint, bool ilu = false) {
   return CoefOff{0,
-                 Tint * (M - R) * 2 * R,
-                 Tint * (M - R) * 2 * R + (M - R),
-                 Tint * (M - R) * 2 * R + (M - R) + R * R,
-                 Tint * (M - R) * 2 * R + (M - R) + 2 * R * R,
-                 Tint * (M - R) * 2 * R + (M - R) + 2 * R * R + (M - R) * R};
+                 interior_size(R, M, Tint, ilu),
+                 interior_size(R, M, Tint, ilu) + (M - R),
+                 interior_size(R, M, Tint, ilu) + (M - R) + R * R,
+                 interior_size(R, M, Tint, ilu) + (M - R) + 2 * R * R,
+                 interior_size(R, M, Tint, ilu) + (M - R) + 2 * R * R + (M - R) * R};
 }
 
 // ---------------------------------------------------------------------------
@@ -76,7 +82,7 @@ struct RedProgram {
 
 // Device view of a segment plan (POD, passed inside kernel arguments).
 struct SegDev {
-  int S, L, M, Tint, Tred, uniform, m, block, ntypes;
+  int S, L, M, Tint, Tred, uniform, m, block, ntypes, ilu;
   const int *lane_type, *lane_start;
   const double *coef64, *red64, *wf64;
   const float *coef32, *red32, *wf32;

@@ -7,6 +7,8 @@ For one (bands, n, precision, grid shape, axis) it times every valid choice of
   * lines_per_wg  -- lines per workgroup (tile width),
   * block_barriers -- wavefront-local or workgroup-wide lane exchanges,
   * x_staging     -- unit-stride lines read directly or through an LDS tile,
+  * interior      -- lane interiors by generalized PCR or banded elimination
+                     (the latter for 8, 12 or 16 rows per lane),
 with HIP events on the launch stream, and returns the fastest.  Results are
 cached in a JSON file keyed by the problem so a process tunes once.
 """
@@ -42,7 +44,9 @@ def candidates(bands, n, precision):
                 continue
             for bb in (0, 1):
                 for xs in (1, 2):
-                    out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb, x_staging=xs))
+                    for it in ((1, 2) if rpl in (8, 12, 16) else (1,)):
+                        out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb, x_staging=xs,
+                                        interior=it))
     return out
 
 
@@ -95,7 +99,7 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
         table.append(dict(c, ms=ms))
         p.close()
     best = min(table, key=lambda r: r["ms"])
-    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers", "x_staging")}
+    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers", "x_staging", "interior")}
     if cache:
         db[key] = {"best": best, "table": table}
         os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -9,10 +9,10 @@ program -- but shares no code with it.
 import numpy as np
 
 
-def _offsets(R, M, T):
+def _offsets(R, M, T, ilu=False):
     N = M - R
     k = 0
-    dinv = T * N * 2 * R
+    dinv = (N * 2 * R) if ilu else (T * N * 2 * R)
     Lt = dinv + N
     Ut = Lt + R * R
     S = Ut + R * R
@@ -24,6 +24,7 @@ def solve_segment(plan, b, seg=0):
     """b: (lines, S) -> x = D_seg^{-1} b by the lane scheme (cyclic or acyclic per plan)."""
     info = plan.info()
     R = info["r"]
+    ilu = bool(info["interior_elimination"])
     types = plan.array(3, seg).astype(int)
     starts = plan.array(4, seg).astype(int)
     L = len(types)
@@ -35,7 +36,7 @@ def solve_segment(plan, b, seg=0):
         Tc = 0
         while (1 << Tc) < Nc:
             Tc += 1
-        if _offsets(R, cand, Tc)["end"] * ntypes == flat.size:
+        if _offsets(R, cand, Tc, ilu)["end"] * ntypes == flat.size:
             M = cand
             break
     assert M is not None
@@ -43,7 +44,7 @@ def solve_segment(plan, b, seg=0):
     T = 0
     while (1 << T) < N:
         T += 1
-    o = _offsets(R, M, T)
+    o = _offsets(R, M, T, ilu)
     coef = flat.reshape(-1, o["end"])
     Tred = 0
     while (1 << Tred) < L:
@@ -55,8 +56,23 @@ def solve_segment(plan, b, seg=0):
     m = np.diff(starts)
     for l in range(L):
         v[l, :, :m[l]] = b[:, starts[l]:starts[l + 1]]
-    # interior generalized PCR
     y = v[:, :, R:].copy()
+    if ilu:  # banded elimination: forward with unit L, backward with U
+        for l in range(L):
+            lu = coef[types[l], o["k"]:o["dinv"]].reshape(N, 2 * R)
+            dv = coef[types[l], o["dinv"]:o["Lt"]]
+            for j in range(N):
+                for q in range(1, R + 1):
+                    if j - q >= 0:
+                        y[l, :, j] -= lu[j, q - 1] * y[l, :, j - q]
+            for j in range(N - 1, -1, -1):
+                acc = y[l, :, j] * dv[j]
+                for q in range(1, R + 1):
+                    if j + q < N:
+                        acc -= lu[j, R + q - 1] * y[l, :, j + q]
+                y[l, :, j] = acc
+        T = 0  # no PCR levels, no final scaling
+    # interior generalized PCR
     for t in range(T):
         s = 1 << t
         yn = y.copy()
@@ -69,7 +85,7 @@ def solve_segment(plan, b, seg=0):
                     if j + q * s < N:
                         yn[l, :, j] -= k[t, j, R + q - 1] * y[l, :, j + q * s]
         y = yn
-    for l in range(L):
+    for l in range(L if not ilu else 0):
         y[l] *= coef[types[l], o["dinv"]:o["Lt"]][None, :]
     # interface RHS
     xt = np.zeros((L, nl, R))

@@ -273,3 +273,17 @@ def test_unit_stride_staging_paths(gpu, n, xs, prec):
     out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), 0).cpu().numpy()
     ref = oracle.apply_axis(f.numpy(), 0, TRI, lo, c)
     assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bands,n,rpl", [(TRI, 512, 16), (TRI, 613, 16), (PENTA, 384, 12), (PENTA, 512, 8)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_interior_elimination(gpu, axis, bands, n, rpl, prec):
+    """Lane interiors by banded elimination (interior=2) match the oracle like generalized PCR."""
+    b = synth.random_uniform(shape_with(axis, n, (10, 18)), seed=n + axis + rpl)
+    plan = cb.Plan(bands, n, rows_per_lane=rpl, interior=2, precision=prec,
+                   refine_iters=(3 if bands is PENTA else 2) if prec == "fp32_refine" else 0)
+    assert plan.info()["interior_elimination"] == 1
+    out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, bands)
+    assert relerr(out, ref) <= 1e-12

@@ -171,3 +171,22 @@ def test_strided_layout_reproduces_oracle(name, n):
         assert np.abs(plan_emulator.solve(p, b, seg) - ref).max() <= 1e-12 * np.abs(ref).max()
     if n == 512:
         assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (8, 16)
+
+
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("n,rpl", [(512, 8), (512, 16), (384, 12), (613, 16), (200, 8)])
+def test_interior_elimination_reproduces_oracle(name, n, rpl):
+    """Lane interiors solved by banded elimination instead of generalized PCR."""
+    bands = _bands(name)
+    p = cb.Plan(bands, n, rows_per_lane=rpl, interior=2, host_only=True)
+    assert p.info()["interior_elimination"] == 1
+    b = np.random.default_rng(n + rpl).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands)
+    assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_interior_elimination_rejected_where_unsupported():
+    with pytest.raises(cb.CbError):
+        cb.Plan([1 / 3, 1, 1 / 3], 512, rows_per_lane=4, interior=2, host_only=True)
+    with pytest.raises(cb.CbError):
+        cb.Plan([1 / 3, 1, 1 / 3], 8192, partitions=16, interior=2, host_only=True)
