@@ -91,8 +91,10 @@ typedef struct {
   int32_t x_staging;      /* unit-stride lines: 0 automatic (= 2), 1 lanes load
                              their rows directly, 2 through a coalesced LDS tile */
   int32_t interior;       /* solve of each lane's interior block D_l: 0 automatic
-                             (= 1), 1 generalized PCR (Sec. 2), 2 banded
-                             elimination in registers (rows_per_lane 8/12/16) */
+                             (1 for unit-stride launches; for strided ones 2
+                             where available), 1 generalized PCR (Sec. 2),
+                             2 banded elimination in registers
+                             (rows_per_lane 8/12/16) */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +
@@ -190,6 +192,7 @@ typedef struct {
   int32_t rows_per_lane_strided; /* layout used by strided launches (P = 1); */
   int32_t lanes_strided;         /* equal to the above when one layout serves both */
   int32_t interior_elimination;  /* 1 when lane interiors use banded elimination */
+  int32_t interior_elimination_strided; /* the same for strided launches */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 
@@ -201,8 +204,8 @@ cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_
 /* Copy one host-side array of a plan (FP64 values; integer arrays are
  * converted) for inspection by tests.  `seg` selects the segment: for a
  * one-partition plan 0 is the lane layout of unit-stride launches and 1 (when
- * lanes_strided differs) that of strided launches; for P > 1 the workgroup
- * partition.  which:
+ * the layout or interior solve of strided launches differs) that of strided
+ * launches; for P > 1 the workgroup partition.  which:
  *   0 lane coefficient blocks [ntypes][block] (layout: k[Tint][N][2r] or,
  *     with elimination, lu[N][2r]; then dinv[N], Lt[r][r], Ut[r][r],
  *     S[N][r], Rm[N][r], N = M - r)
@@ -213,6 +216,7 @@ cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_
  *   6 workgroup L~,U~ [P][2][r][r]   7 partition starts [P+1]
  *   8 reduced-solve program: term ranges [phases][P+1]
  *   9 its source rows per term          10 its matrices per term [r][r]
+ *  11 segment shape: S, L, M, r, Tint, Tred, elimination, uniform, cyclic
  * Writes min(cap, size) values; *len receives the full size. */
 cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *out, int64_t cap,
                             int64_t *len);

@@ -56,7 +56,8 @@ class PlanInfo(ctypes.Structure):
                  "red_detach_steps")] + [("device_bytes", ctypes.c_int64),
                                          ("rows_per_lane_strided", ctypes.c_int32),
                                          ("lanes_strided", ctypes.c_int32),
-                                         ("interior_elimination", ctypes.c_int32)]
+                                         ("interior_elimination", ctypes.c_int32),
+                                         ("interior_elimination_strided", ctypes.c_int32)]
 
 
 def lib():

@@ -607,6 +607,7 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->rows_per_lane_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].M;
   info->lanes_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].L;
   info->interior_elimination = p.segs.empty() ? 0 : p.segs[0].ilu;
+  info->interior_elimination_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].ilu;
   return CB_OK;
 }
 
@@ -641,6 +642,9 @@ cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *
     case 8: v.assign(p.prog.row_off.begin(), p.prog.row_off.end()); break;
     case 9: v.assign(p.prog.src.begin(), p.prog.src.end()); break;
     case 10: v = p.prog.mats; break;
+    case 11: v = {(double)s.S, (double)s.L, (double)s.M, (double)s.R, (double)s.Tint, (double)s.Tred,
+                  (double)s.ilu, (double)s.uniform, (double)s.cyclic};
+      break;
     default: return fail(CB_ERR_INVALID_ARG, "unknown array id");
   }
   *len = (int64_t)v.size();

@@ -630,8 +630,12 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   sp.Tred = ceil_log2(L);
   sp.uniform = uni;
   sp.m_uniform = m_uni;
-  // interior solve: 1 generalized PCR, 2 elimination; automatic = PCR
-  sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16)) ? 1 : 0;
+  // interior solve: 0/1 generalized PCR, 2 elimination, 3 elimination where
+  // a kernel exists for it (8 or 16 rows per lane, or 12 on uniform lanes)
+  sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16)) ||
+                   (interior == 3 && (M == 8 || M == 16 || (M == 12 && uni)))
+               ? 1
+               : 0;
   if (interior == 2 && !sp.ilu) {
     msg = "interior elimination needs rows_per_lane 8, 12 or 16";
     return CB_ERR_UNSUPPORTED;
@@ -781,10 +785,15 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     if (s != CB_OK) return s;
     p.seg_s = 0;
     if (!d.rows_per_lane) {
+      // strided lines: lane interiors by elimination unless asked otherwise
+      // (fewer live registers per lane; PCR if a pivot vanishes)
       SegPlan alt;
-      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, d.interior);
+      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max,
+                        d.interior ? d.interior : 3);
+      if (s != CB_OK && d.interior == 0)
+        s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, 1);
       if (s != CB_OK) return s;
-      if (alt.M != p.segs[0].M || alt.L != p.segs[0].L) {
+      if (alt.M != p.segs[0].M || alt.L != p.segs[0].L || alt.ilu != p.segs[0].ilu) {
         p.segs.push_back(std::move(alt));
         p.seg_s = 1;
       }

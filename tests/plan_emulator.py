@@ -24,7 +24,7 @@ def solve_segment(plan, b, seg=0):
     """b: (lines, S) -> x = D_seg^{-1} b by the lane scheme (cyclic or acyclic per plan)."""
     info = plan.info()
     R = info["r"]
-    ilu = bool(info["interior_elimination"])
+    ilu = bool(plan.array(11, seg)[6])
     types = plan.array(3, seg).astype(int)
     starts = plan.array(4, seg).astype(int)
     L = len(types)

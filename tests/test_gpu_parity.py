@@ -278,12 +278,13 @@ def test_unit_stride_staging_paths(gpu, n, xs, prec):
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("bands,n,rpl", [(TRI, 512, 16), (TRI, 613, 16), (PENTA, 384, 12), (PENTA, 512, 8)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
-def test_interior_elimination(gpu, axis, bands, n, rpl, prec):
-    """Lane interiors by banded elimination (interior=2) match the oracle like generalized PCR."""
+@pytest.mark.parametrize("interior", [1, 2])
+def test_interior_solves(gpu, axis, bands, n, rpl, prec, interior):
+    """Lane interiors by generalized PCR (1) or banded elimination (2) on every axis."""
     b = synth.random_uniform(shape_with(axis, n, (10, 18)), seed=n + axis + rpl)
-    plan = cb.Plan(bands, n, rows_per_lane=rpl, interior=2, precision=prec,
+    plan = cb.Plan(bands, n, rows_per_lane=rpl, interior=interior, precision=prec,
                    refine_iters=(3 if bands is PENTA else 2) if prec == "fp32_refine" else 0)
-    assert plan.info()["interior_elimination"] == 1
+    assert plan.info()["interior_elimination"] == interior - 1
     out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
     ref = oracle.solve_axis(b.numpy(), axis, bands)
     assert relerr(out, ref) <= 1e-12
