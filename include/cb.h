@@ -100,7 +100,9 @@ typedef struct {
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +
  * i1*stride[1] + i2*stride[2]].  Index 0 is x.  A C-order (nz,ny,nx) array
  * has n = {nx,ny,nz}, stride = {1,nx,nx*ny}.  Strides are in elements and
- * must be positive; lines along `axis` have n[axis] == plan n. */
+ * must be positive; lines along `axis` have n[axis] == plan n.  The other two
+ * extents may be 0 (an empty grid: the call succeeds, launches nothing and
+ * does not read the data pointers, which may then be NULL). */
 typedef struct {
   int64_t n[3];
   int64_t stride[3];

@@ -146,8 +146,9 @@ cb_status geometry(const cb_grid *g, int axis, Geo &o) {
   if (!g) return fail(CB_ERR_INVALID_ARG, "grid is NULL");
   if (axis < 0 || axis > 2) return fail(CB_ERR_INVALID_ARG, "axis must be 0, 1 or 2");
   for (int i = 0; i < 3; ++i)
-    if (g->n[i] <= 0 || g->stride[i] <= 0)
-      return fail(CB_ERR_INVALID_ARG, "grid extents and strides must be positive");
+    if (g->n[i] < 0 || g->stride[i] <= 0)
+      return fail(CB_ERR_INVALID_ARG, "grid extents must be non-negative and strides positive");
+  if (g->n[axis] == 0) return fail(CB_ERR_INVALID_ARG, "grid extent along the solve axis must be positive");
   const int u = axis == 0 ? 1 : 0, v = axis == 2 ? 1 : 2;
   o.n = g->n[axis];
   o.rs = g->stride[axis];
@@ -159,6 +160,8 @@ cb_status geometry(const cb_grid *g, int axis, Geo &o) {
 }
 
 int64_t span_elems(const cb_grid *g) {
+  for (int i = 0; i < 3; ++i)
+    if (g->n[i] == 0) return 0;  // empty grid: no element
   int64_t s = 1;
   for (int i = 0; i < 3; ++i) s += (g->n[i] - 1) * g->stride[i];
   return s;
@@ -398,6 +401,7 @@ cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t
   if (s) return s;
   Geo g;
   if ((s = geometry(grid, axis, g))) return s;
+  if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
   if (!f || !b) return fail(CB_ERR_INVALID_ARG, "f and b must be non-NULL");
   if (overlap(f, b, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and b overlap");
   StencilArgs a;
@@ -428,6 +432,9 @@ cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const doub
   Geo g;
   if ((s = geometry(grid, axis, g))) return s;
   if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
+    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
+  if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
   if (!b || !x) return fail(CB_ERR_INVALID_ARG, "b and x must be non-NULL");
   if (b != x && overlap(b, x, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "b and x overlap");
   if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
@@ -444,12 +451,13 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
   Geo g;
   if ((s = geometry(grid, axis, g))) return s;
   if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (!plan->p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "the fused stencil needs a cyclic plan");
+  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
+    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
+  if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
   if (!f || !out) return fail(CB_ERR_INVALID_ARG, "f and out must be non-NULL");
   if (overlap(f, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and out overlap");
-  if (!plan->p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "the fused stencil needs a cyclic plan");
   if (plan->p.P != 1) {
-    if (plan->p.precision != CB_FP64)
-      return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
     return launch_wg(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
   }
   return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
@@ -488,7 +496,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     Geo g;
     if ((s = geometry(&it.grid, it.axis, g))) return s;
     if (g.n != p.n) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: grid extent differs from plan n");
-    if (!it.in || !it.out) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: NULL data pointer");
+    if (g.nlines > 0 && (!it.in || !it.out)) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: NULL data pointer");
     if (overlap(it.in, it.out, span_elems(&it.grid)))
       return fail(CB_ERR_INVALID_ARG, "cb_batch_build: in and out overlap");
     if (it.stencil) {

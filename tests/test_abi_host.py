@@ -39,8 +39,12 @@ def test_null_and_bad_arguments(L):
     bad = cb.StencilC(-4, 0, (ctypes.c_double * 7)())
     assert L.cb_rhs_stencil(ctypes.byref(bad), ctypes.byref(g), 0, ctypes.c_void_p(64),
                             ctypes.c_void_p(1 << 20), None) == cb.CB_ERR_INVALID_ARG
-    g0 = grid((16, 0, 4))
+    g0 = grid((0, 8, 4))  # empty along the solve axis
     assert L.cb_rhs_stencil(ctypes.byref(st.c), ctypes.byref(g0), 0, ctypes.c_void_p(64),
+                            ctypes.c_void_p(1 << 20), None) == cb.CB_ERR_INVALID_ARG
+    gneg = grid((16, 8, 4))
+    gneg.n[1] = -1
+    assert L.cb_rhs_stencil(ctypes.byref(st.c), ctypes.byref(gneg), 0, ctypes.c_void_p(64),
                             ctypes.c_void_p(1 << 20), None) == cb.CB_ERR_INVALID_ARG
     # overlapping input and output
     assert L.cb_rhs_stencil(ctypes.byref(st.c), ctypes.byref(g), 0, ctypes.c_void_p(4096),
@@ -61,3 +65,13 @@ def test_plan_info_of_host_plan(L):
     assert (i["r"], i["n"], i["partitions"], i["lanes"], i["rows_per_lane"]) == (2, 8192, 16, 64, 8)
     assert i["red_pcr_steps"] == 4 and i["red_detach_steps"] == 0
     assert i["device_bytes"] == 0
+
+
+def test_empty_grid_is_a_noop(L):
+    """A grid with no lines succeeds and launches nothing (so it needs no GPU)."""
+    st = cb.Stencil(-1, [1.0, 2.0, 3.0])
+    for n, axis in (((16, 0, 4), 0), ((0, 8, 4), 1), ((16, 8, 0), 0)):
+        g = grid(n)
+        g.stride[0], g.stride[1], g.stride[2] = 1, 16, 128
+        assert L.cb_rhs_stencil(ctypes.byref(st.c), ctypes.byref(g), axis, ctypes.c_void_p(64),
+                                ctypes.c_void_p(1 << 20), None) == cb.CB_OK

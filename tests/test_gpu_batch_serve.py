@@ -87,6 +87,22 @@ def test_batched_solve_items_and_penta(gpu):
         assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
 
 
+def test_batch_with_empty_items(gpu):
+    """Items with no lines (first, middle, last) take no tiles; the others are solved."""
+    plan = cb.Plan(TRI, 64, rows_per_lane=8)
+    items, refs = [], []
+    for k, shape in enumerate(((0, 3, 64), (4, 3, 64), (2, 0, 64), (3, 5, 64), (0, 0, 64))):
+        b = synth.random_uniform(shape, seed=k).to(gpu)
+        out = torch.full_like(b, 7.0)
+        items.append((plan, None, b, out, 0))
+        refs.append(oracle.solve_axis(b.cpu().numpy(), 0, TRI) if b.numel() else None)
+    launch(batch(items), max_ctas=3)
+    torch.cuda.synchronize()
+    for it, ref in zip(items, refs):
+        if ref is not None:
+            assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
+
+
 def test_graph_replay_of_batched_launch(gpu):
     """Captured launch replayed several times with eager work in between."""
     f, _ = synth.random_modes((24, 40, 32), seed=4)

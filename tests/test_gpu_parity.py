@@ -288,3 +288,18 @@ def test_interior_solves(gpu, axis, bands, n, rpl, prec, interior):
     out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
     ref = oracle.solve_axis(b.numpy(), axis, bands)
     assert relerr(out, ref) <= 1e-12
+
+
+def test_empty_grids(gpu):
+    """Grids with no lines: every entry point succeeds and writes nothing."""
+    lo, c = deriv_stencil(schemes.DERIV6, 64)
+    st = cb.Stencil(lo, c)
+    for P in (1, 2):
+        plan = cb.Plan(TRI, 64, partitions=P)
+        for shape, axis in (((3, 0, 64), 0), ((0, 64, 5), 1), ((64, 4, 0), 2)):
+            f = torch.zeros(shape, dtype=torch.float64, device=gpu)
+            out = torch.empty_like(f)
+            cb.solve(plan, f, axis, out=out)
+            cb.apply_derivative(plan, st, f, axis, out=out)
+            cb.rhs_stencil(st, f, axis, out=out)
+    torch.cuda.synchronize()
