@@ -282,6 +282,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
   const int L = p.L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
+  if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
   NT = std::min(std::max(NT, L), 1024);
   // keep the LDS of phase C (lane exchange + reduced-system state) within 64 KB
   const int RSw = 2 * std::max(p.R, Q);
@@ -289,7 +290,16 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   for (const SegPlan &sp : p.segs) coef_doubles = std::max(coef_doubles, (size_t)sp.ntypes * sp.block);
   const bool coef_lds = coef_doubles * 8 <= 16384;
   const size_t extra = coef_lds ? coef_doubles : 0;
-  while (NT > L && ((size_t)NT * 2 * RSw + (size_t)2 * (NT / L) * p.P * p.R + extra) * 8 > 65536) NT /= 2;
+  // unit-stride lines are loaded and stored through an LDS tile of W lines
+  const bool stage_x = mode == MODE_X && p.desc.x_staging != 1;
+  int smax = 0;
+  for (const SegPlan &sp : p.segs) smax = std::max(smax, sp.S);
+  const int64_t pitch = stage_x ? smax + smax / p.M + 1 : 0;
+  auto lds_c_of = [&](int nt) {
+    return ((size_t)nt * 2 * RSw + (size_t)2 * (nt / L) * p.P * p.R + extra + (size_t)(nt / L) * pitch) * 8;
+  };
+  while (NT > L && lds_c_of(NT) > 65536) NT /= 2;
+  if (lds_c_of(NT) > 65536) return fail(CB_ERR_UNSUPPORTED, "partition too long for one workgroup");
   const int W = NT / L;
   WgArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -310,6 +320,10 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.coef_lds = coef_lds ? 1 : 0;
   a.coef_off_a = (int64_t)NT * 2 * RSw;
   a.coef_off_c = a.coef_off_a + (int64_t)2 * W * p.P * p.R;
+  a.stage_x = stage_x ? 1 : 0;
+  a.stage_off_a = a.coef_off_a + (int64_t)extra;
+  a.stage_off_c = a.coef_off_c + (int64_t)extra;
+  a.stage_pitch = pitch;
   a.segs = p.segdev;
   a.wg_start = p.d_wg_start;
   a.bands = p.d_bands;
@@ -330,8 +344,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int64_t tiles = (g.nlines + W - 1) / W;
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
-  const size_t lds_a = ((size_t)a.coef_off_a + extra) * sizeof(double);
-  const size_t lds_c = ((size_t)a.coef_off_c + extra) * sizeof(double);
+  const size_t lds_a = ((size_t)a.stage_off_a + (size_t)W * pitch) * sizeof(double);
+  const size_t lds_c = ((size_t)a.stage_off_c + (size_t)W * pitch) * sizeof(double);
   e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
   hipError_t e2 = hipFreeAsync(scratch, stream);

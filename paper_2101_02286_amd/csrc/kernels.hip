@@ -94,40 +94,89 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
 // couplings to the interface unknowns x~_i (first r rows of D_i) and
 // x~_{i+1} (last r rows), so the solve returns x_i = D_i^{-1}[b_i - L_i x~_i
 // - U_i x~_{i+1}] directly (Eq. (9)).
+// Staged unit-stride rows: the L lanes of a line read (or write) its S
+// interior rows with consecutive 8-byte words through an LDS tile in which one
+// pad word follows every M words.
+template <int M>
+__device__ __forceinline__ int tile_at(int e) {
+  return e + e / M;
+}
+
 template <int R, int M, int MODE, int Q, bool ADJ>
 __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
-                                                  int &start, int &m, double *coef_lds,
+                                                  int &start, int &m, double *coef_lds, double *tb,
                                                   const double (&xi)[R], const double (&xi1)[R]) {
   const SegDev &sg = a.segs[part];
   if (a.coef_lds) stage_coef<double>(sg, coef_lds, p.tid, blockDim.x);
   start = sg.lane_start[p.l];
   m = sg.lane_start[p.l + 1] - start;
   const int type = sg.lane_type[p.l];
+  const int S = sg.S;
   const int64_t seg0 = a.wg_start[part] + R;  // first row of the interior block D_i
   const int64_t row0 = seg0 + start;
-  const double *in = a.in + base + row0 * a.rs;
+  const bool staged = MODE == MODE_X && tb != nullptr;
+  if (staged) {
+    const double *lin = a.in + base + seg0;
+    double t[M];
 #pragma unroll
-  for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      t[k] = (active && e < S) ? __builtin_nontemporal_load(lin + e) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (e < S) tb[tile_at<M>(e)] = t[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = k < m ? tb[tile_at<M>(start + k)] : 0.0;
+  } else {
+    const double *in = a.in + base + row0 * a.rs;
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
+  }
   if (Q > 0) {  // fused stencil; the halo at the block's ends comes from global memory
     constexpr int QQ = Q > 0 ? Q : 1;
     double fp[QQ], fn[QQ];
-    halo<QQ, M>(v, m, false, p, xc, fp, fn);
-    if (p.l == 0) {
+    if (staged) {  // neighbours inside D_i from the tile, beyond its ends from global memory
 #pragma unroll
       for (int i = 0; i < QQ; ++i) {
-        int64_t r = seg0 - QQ + i;
-        r = r < 0 ? r + a.n : r;
-        fp[i] = active ? a.in[base + r * a.rs] : 0.0;
+        const int e0 = start - QQ + i, e1 = start + m + i;
+        if (e0 >= 0) {
+          fp[i] = tb[tile_at<M>(e0)];
+        } else {
+          int64_t r = seg0 + e0;
+          r = r < 0 ? r + a.n : r;
+          fp[i] = active ? a.in[base + r * a.rs] : 0.0;
+        }
+        if (e1 < S) {
+          fn[i] = tb[tile_at<M>(e1)];
+        } else {
+          int64_t r = seg0 + e1;
+          r = r >= a.n ? r - a.n : r;
+          fn[i] = active ? a.in[base + r * a.rs] : 0.0;
+        }
       }
-    }
-    if (p.l == p.L - 1) {
-      const int64_t end = a.wg_start[part + 1];
+    } else {
+      halo<QQ, M>(v, m, false, p, xc, fp, fn);
+      if (p.l == 0) {
 #pragma unroll
-      for (int i = 0; i < QQ; ++i) {
-        int64_t r = end + i;
-        r = r >= a.n ? r - a.n : r;
-        fn[i] = active ? a.in[base + r * a.rs] : 0.0;
+        for (int i = 0; i < QQ; ++i) {
+          int64_t r = seg0 - QQ + i;
+          r = r < 0 ? r + a.n : r;
+          fp[i] = active ? a.in[base + r * a.rs] : 0.0;
+        }
+      }
+      if (p.l == p.L - 1) {
+        const int64_t end = a.wg_start[part + 1];
+#pragma unroll
+        for (int i = 0; i < QQ; ++i) {
+          int64_t r = end + i;
+          r = r >= a.n ? r - a.n : r;
+          fn[i] = active ? a.in[base + r * a.rs] : 0.0;
+        }
       }
     }
     double bb[M];
@@ -142,7 +191,6 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     for (int k = 0; k < M; ++k) v[k] = bb[k];
   }
   if (ADJ) {
-    const int S = sg.S;
     constexpr int W2 = 2 * R + 1;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -178,8 +226,9 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   double v[M];
   int start, m;
   const double none[R] = {};
-  wg_solve_interior<R, M, MODE, Q, false>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a, none,
-                                          none);
+  wg_solve_interior<R, M, MODE, Q, false>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a,
+                                          a.stage_x ? smem + a.stage_off_a + (size_t)p.li * a.stage_pitch : nullptr,
+                                          none, none);
   if (!active) return;
   double *sc = a.scratch + (line * a.P + part) * 3 * R;
   if (p.l == 0) {
@@ -284,13 +333,32 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
   Xchg xc{smem, RS, NT, 0, true};
   double v[M];
   int start, m;
-  wg_solve_interior<R, M, MODE, Q, true>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c, xi, xi1);
-  if (!active) return;
-  const int64_t row0 = a.wg_start[part] + R + start;
-  double *out = a.out + base + row0 * a.rs;
+  double *tb = a.stage_x ? smem + a.stage_off_c + (size_t)p.li * a.stage_pitch : nullptr;
+  wg_solve_interior<R, M, MODE, Q, true>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c, tb, xi,
+                                         xi1);
+  const int64_t seg0 = a.wg_start[part] + R;
+  if (MODE == MODE_X && tb != nullptr) {
+    // mirror of the staged load: every lane has finished reading the tile
+    // (its stencil halo) before any lane overwrites it
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < M; ++k)
-    if (k < m) out[k * a.rs] = v[k];
+    for (int k = 0; k < M; ++k)
+      if (k < m) tb[tile_at<M>(start + k)] = v[k];
+    __syncthreads();
+    const int S = a.segs[part].S;
+    double *lout = a.out + base + seg0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int e = p.l + k * p.L;
+      if (active && e < S) __builtin_nontemporal_store(tb[tile_at<M>(e)], lout + e);
+    }
+  } else if (active) {
+    double *out = a.out + base + (seg0 + start) * a.rs;
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      if (k < m) out[k * a.rs] = v[k];
+  }
+  if (!active) return;
   if (p.l == 0) {
     const int64_t g0 = a.wg_start[part];
 #pragma unroll

@@ -14,6 +14,7 @@ struct DivMagic {
   uint32_t d, mul, s1, s2;
 };
 inline DivMagic make_divmagic(uint32_t d) {
+  if (d == 0) d = 1;  // an empty grid has no line to index
   uint32_t l = 0;
   while (l < 32 && (uint64_t(1) << l) < d) ++l;
   DivMagic m;
@@ -51,6 +52,8 @@ struct WgArgs {
   int lgL, lgW, P, nphase;
   int coef_lds;              // stage each partition's coefficient blocks in LDS
   int64_t coef_off_a, coef_off_c;  // their LDS offsets (doubles) in phases A and C
+  int stage_x;               // unit-stride lines: load/store through an LDS tile
+  int64_t stage_off_a, stage_off_c, stage_pitch;  // its offsets and per-line pitch (doubles)
   const SegDev *segs;        // [P]
   const int *wg_start;       // [P+1]
   const double *bands;       // [n][2R+1] band rows of the line (Eq. (9) couplings)
