@@ -260,7 +260,7 @@ def mode_batched(args):
             for ax in range(3):
                 n = f.shape[2 - ax]
                 if n not in plans:
-                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=2, rows_per_lane=8),
+                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=2),
                                 deriv_stencil(n, a, b))
                 items.append((plans[n][0], plans[n][1], f, torch.empty_like(f), ax))
         arr = (cb.BatchItem * len(items))()

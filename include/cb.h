@@ -156,16 +156,20 @@ typedef struct {
 } cb_batch_item;
 
 /* Batched execution: the lines of many items -- uneven grids, any axes,
- * different plans -- run in ONE persistent kernel launch that takes tiles
- * from a device work queue.  Every plan in a batch must have partitions = 1,
- * the same r, the same rows_per_lane (8 or 16) and the same arithmetic
- * (FP64, or FP32 with or without refinement); n, axis, grid, stencil and
- * refinement count may differ.  Plans must be cyclic when a stencil is given.
+ * different plans -- run in persistent kernel launches that take line tiles
+ * from device work queues: ONE launch per kernel class present in the batch
+ * (a class is r, rows per lane, arithmetic, uniform or general lane layout,
+ * and interior solve of the lane layout an item's row stride selects; a
+ * batch of plans built alike for one scheme and precision is usually one or
+ * two classes).  Every plan must have partitions = 1 and be cyclic when a
+ * stencil is given; n, axis, grid, stencil, precision and refinement count
+ * may differ between items.  Each line goes through the same arithmetic as
+ * in a single cb_solve / cb_apply_derivative call with the same plan.
  *
  * `workspace` is a caller-owned DEVICE buffer of at least
  * cb_batch_workspace_size(n_items) bytes holding the queue and work table.
  * cb_batch_build validates the items and writes the table (it waits for the
- * copy to finish).  cb_batch_launch enqueues the persistent kernel only: it
+ * copy to finish).  cb_batch_launch enqueues the persistent kernels only: it
  * allocates nothing, copies nothing and leaves the queue reset when it
  * finishes, so it may be captured in a HIP graph and replayed.  Launches
  * that share a workspace must not overlap in time.  `max_ctas` caps the

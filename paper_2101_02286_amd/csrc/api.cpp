@@ -23,9 +23,19 @@ namespace {
 
 thread_local std::string g_err;
 
-// kernel selection (r, rows_per_lane, fp32) of each built batch workspace
+// The launches of each built batch workspace: one persistent kernel per
+// kernel class, with its queue header, work-table slice and LDS size.
+struct BatchLaunch {
+  const void *fn;
+  size_t hdr_off, items_off, lds;
+};
 std::mutex g_batch_mu;
-std::map<void *, std::array<int, 4>> g_batch_sel;  // + LDS bytes of staged coefficients
+std::map<void *, std::vector<BatchLaunch>> g_batch_sel;
+
+// batch workspace layout: kBatchHdrBytes per class header (at most one class
+// per item), then the work table from a 256-byte boundary
+constexpr size_t kBatchHdrBytes = 64;
+size_t batch_items_offset(size_t n_items) { return (std::max<size_t>(n_items, 1) * kBatchHdrBytes + 255) / 256 * 256; }
 
 cb_status fail(cb_status s, const std::string &m) {
   g_err = m;
@@ -195,10 +205,10 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
   const bool fp32 = p.precision != CB_FP64;
-  // MODE_X needs unit row stride; the vectorised uniform path also needs
-  // 16-byte aligned line starts.
+  // MODE_X needs unit row stride; the vectorised direct loads of uniform
+  // layouts (no LDS tile) also need 16-byte aligned line starts.
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
-  if (mode == MODE_X && uni) {
+  if (mode == MODE_X && uni && p.desc.x_staging == 1) {
     const bool al = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
                     (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
     if (!al) mode = MODE_S;
@@ -218,17 +228,16 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   } else {
     W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
-  // LDS: two exchange regions of max(2Q, 2r) doubles per thread, at most 64 KB
-  // exchange region size per thread (see line_region in kernels.hip)
-  const int RS = std::max(2 * Q, 2 * p.R);
+  // LDS: two exchange regions of max(2Q, 2r) doubles per thread (2r when the
+  // unit-stride tile is staged: its halo comes from the tile), at most 64 KB
+  const bool stage_x = mode == MODE_X && p.desc.x_staging != 1;
+  const int RS = stage_x ? 2 * p.R : std::max(2 * Q, 2 * p.R);
   // general layouts stage their coefficient blocks in LDS when they are small
   const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp32 ? 4 : 8);
   const bool coef_lds = !uni && coef_bytes <= 16384;
   const size_t coef_dbl = coef_lds ? (coef_bytes + 7) / 8 : 0;
   // unit-stride lines of general layouts (and, on request, uniform ones) are
   // loaded and stored through an LDS tile of W lines
-  const int xs = p.desc.x_staging;
-  const bool stage_x = mode == MODE_X && xs != 1;
   const int64_t pitch = stage_x ? g.n + g.n / sp.M + 1 : 0;
   auto lds_of = [&](int w) {
     return ((size_t)w * L * 2 * RS + coef_dbl + (size_t)w * pitch) * sizeof(double);
@@ -478,35 +487,32 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
 }
 
 size_t cb_batch_workspace_size(int32_t n_items) {
-  return 256 + (size_t)(n_items > 0 ? n_items : 0) * sizeof(BatchItemDev);
+  const size_t n = (size_t)(n_items > 0 ? n_items : 0);
+  return batch_items_offset(n) + n * sizeof(BatchItemDev);
 }
 
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
                          void *stream) {
   if (!items || n_items <= 0) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: no items");
-  if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace is NULL");
-  if (workspace_bytes < cb_batch_workspace_size(n_items))
-    return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace too small");
+  if (!workspace || workspace_bytes < cb_batch_workspace_size(n_items))
+    return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace missing or too small");
+  struct Cls {
+    int R, M, fp;
+    bool uni, ilu;
+    const void *fn;
+    size_t lds;
+    std::vector<int> members;
+  };
+  std::vector<Cls> cls;
+  std::vector<int> cls_of(n_items);
   std::vector<BatchItemDev> tab(n_items);
-  int R0 = -1, M0 = -1, fp0 = -1;
-  int64_t tiles = 0;
-  size_t coef_max = 0;
+  std::vector<int64_t> ntiles(n_items);
   for (int i = 0; i < n_items; ++i) {
     const cb_batch_item &it = items[i];
     cb_status s = check_plan_for_solve(it.plan);
     if (s) return s;
     const Plan &p = it.plan->p;
     if (p.P != 1) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: plans must have partitions = 1");
-    const int fp = p.precision != CB_FP64;
-    if (R0 < 0) {
-      R0 = p.R;
-      M0 = p.M;
-      fp0 = fp;
-    } else if (p.R != R0 || p.M != M0 || fp != fp0) {
-      return fail(CB_ERR_INVALID_ARG, "cb_batch_build: plans differ in r, rows_per_lane or precision");
-    }
-    if (p.M != 8 && p.M != 16) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: rows_per_lane must be 8 or 16");
-    if (p.segs[0].ilu) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: plans must use the PCR interior solve");
     Geo g;
     if ((s = geometry(&it.grid, it.axis, g))) return s;
     if (g.n != p.n) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: grid extent differs from plan n");
@@ -517,10 +523,45 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       if ((s = check_stencil(it.stencil))) return s;
       if (!p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: a stencil needs a cyclic plan");
     }
-    const int L = p.L;
+    if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: more than 2^31 lines");
+    // the plan's lane layout for this item's row stride, as a single launch uses
+    const int si = g.rs == 1 ? 0 : p.seg_s;
+    const SegPlan &sp = p.segs[si];
+    const int fp = p.precision != CB_FP64;
+    const bool uni = sp.uniform != 0, ilu = sp.ilu != 0;
+    const void *fn = find_batch_kernel(p.R, sp.M, fp, uni, ilu);
+    if (!fn) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: no batched kernel for an item's lane layout");
+    const int L = sp.L;
     if (L > kBatchThreads) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: line needs too many lanes");
     const int W = kBatchThreads / L;
-    if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: more than 2^31 lines");
+    // tile shape and LDS: unit-stride lines through an LDS tile when it fits
+    // in 64 KB (halo from the tile, exchange regions of 2r values), else with
+    // direct loads; strided lines as W adjacent lines (128-byte segments)
+    const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp ? 4 : 8);
+    const size_t coef_dbl_if = (coef_bytes + 7) / 8;
+    const int RSs = std::max(6, 2 * p.R);  // stencil halo of +-3 rows
+    auto lds_bytes = [&](int RS, bool coef, int64_t pitch) {
+      return ((size_t)W * L * 2 * RS + (coef ? coef_dbl_if : 0) + (size_t)W * pitch) * 8;
+    };
+    int mode = g.rs == 1 ? MODE_X : MODE_S;
+    bool stage = false, coef_lds = false;
+    int64_t pitch = 0;
+    int RS = RSs;
+    if (mode == MODE_X) {
+      const int64_t pt = g.n + g.n / sp.M + 1;
+      if (lds_bytes(2 * p.R, false, pt) <= 65536) {
+        stage = true;
+        pitch = pt;
+        RS = 2 * p.R;
+      } else if (uni) {  // direct loads of a uniform layout use 16-byte vectors
+        const bool al = ((uintptr_t)it.in % 16 == 0) && ((uintptr_t)it.out % 16 == 0) &&
+                        (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
+        if (!al) mode = MODE_S;
+      }
+    }
+    coef_lds = !uni && coef_bytes <= 16384 && lds_bytes(RS, true, pitch) <= 65536;
+    const size_t lds = lds_bytes(RS, coef_lds, pitch);
+    if (lds > 65536) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: an item's tile exceeds 64 KB of LDS");
     BatchItemDev &d = tab[i];
     std::memset(&d, 0, sizeof(d));
     LineArgs &a = d.a;
@@ -532,71 +573,90 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.sv = g.sv;
     a.rs = g.rs;
     a.n = (int)g.n;
-    a.stage_x = 0;  // the batched launch reads unit-stride lines directly
     a.nudiv = make_divmagic((uint32_t)g.nu);
     a.lgL = ilog2(L);
     a.lgW = ilog2(W);
-    a.block_sync = 1;
+    // lanes of a unit-stride line are adjacent threads: with L <= 64 a line
+    // lies in one wavefront and its exchanges need no workgroup barrier
+    a.block_sync = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 0 : 1;
     a.refine_iters = p.refine_iters;
-    a.seg = p.segdev_host[0];
-    {
-      const SegPlan &sp = p.segs[0];
-      const size_t cb = sp.uniform ? 0 : (size_t)sp.ntypes * sp.block * (fp ? 4 : 8);
-      a.coef_lds = (!sp.uniform && cb <= 16384) ? 1 : 0;
-      if (a.coef_lds) coef_max = std::max(coef_max, cb);
-    }
+    a.coef_lds = coef_lds ? 1 : 0;
+    a.stage_x = stage ? 1 : 0;
+    a.stage_off = (int64_t)W * L * 2 * RS + (coef_lds ? (int64_t)coef_dbl_if : 0);
+    a.stage_pitch = pitch;
+    a.seg = p.segdev_host[si];
     if (it.stencil) stencil_q(it.stencil, a.stc);
     else a.stc[3] = 1.0;  // identity stencil: b = input
     for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
     a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
-    d.mode = g.rs == 1 ? MODE_X : MODE_S;
-    d.tile_begin = tiles;
-    tiles += (g.nlines + W - 1) / W;
+    d.mode = mode;
+    ntiles[i] = (g.nlines + W - 1) / W;
+    int c = 0;
+    while (c < (int)cls.size() && !(cls[c].fn == fn)) ++c;
+    if (c == (int)cls.size()) cls.push_back(Cls{p.R, sp.M, fp, uni, ilu, fn, 0, {}});
+    cls[c].lds = std::max(cls[c].lds, lds);
+    cls[c].members.push_back(i);
+    cls_of[i] = c;
   }
   for (int i = 0; i < n_items; ++i)
     for (int j = i + 1; j < n_items; ++j)
       if (overlap2(items[i].out, span_elems(&items[i].grid), items[j].out, span_elems(&items[j].grid)))
         return fail(CB_ERR_INVALID_ARG, "cb_batch_build: outputs of two items overlap");
+  // workspace: one queue header per class, then the work table grouped by class
   std::vector<char> host(cb_batch_workspace_size(n_items), 0);
-  BatchHdr h;
-  std::memset(&h, 0, sizeof(h));
-  h.n_items = n_items;
-  h.total_tiles = tiles;
-  std::memcpy(host.data(), &h, sizeof(h));
-  std::memcpy(host.data() + 256, tab.data(), sizeof(BatchItemDev) * tab.size());
+  std::vector<BatchLaunch> launches;
+  size_t slot = 0;
+  for (size_t c = 0; c < cls.size(); ++c) {
+    int64_t tiles = 0;
+    for (int i : cls[c].members) {
+      tab[i].tile_begin = tiles;
+      tiles += ntiles[i];
+      std::memcpy(host.data() + batch_items_offset(n_items) + (slot++) * sizeof(BatchItemDev), &tab[i],
+                  sizeof(BatchItemDev));
+    }
+    BatchHdr h;
+    std::memset(&h, 0, sizeof(h));
+    h.n_items = (int)cls[c].members.size();
+    h.total_tiles = tiles;
+    std::memcpy(host.data() + c * kBatchHdrBytes, &h, sizeof(h));
+    launches.push_back({cls[c].fn, c * kBatchHdrBytes,
+                        batch_items_offset(n_items) + (slot - cls[c].members.size()) * sizeof(BatchItemDev),
+                        cls[c].lds});
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_build: copy");
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_batch_sel[workspace] = {R0, M0, fp0, (int)coef_max};
+  g_batch_sel[workspace] = std::move(launches);
   return CB_OK;
 }
 
 cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace is NULL");
-  std::array<int, 4> sel;
+  std::vector<BatchLaunch> ls;
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     auto itr = g_batch_sel.find(workspace);
     if (itr == g_batch_sel.end()) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace was not built");
-    sel = itr->second;
+    ls = itr->second;
   }
-  const void *fn = find_batch_kernel(sel[0], sel[1], sel[2]);
-  if (!fn) return fail(CB_ERR_UNSUPPORTED, "cb_batch_launch: no kernel for this batch");
-  int dev = 0, ncu = 0, per_cu = 0;
+  int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = (size_t)kBatchThreads * 2 * 6 * sizeof(double) + (size_t)sel[3];
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
-  int ctas = std::max(1, ncu * std::max(per_cu, 1));
-  if (max_ctas > 0) ctas = std::min(ctas, (int)max_ctas);
-  BatchHdr *hdr = static_cast<BatchHdr *>(workspace);
-  const BatchItemDev *items = reinterpret_cast<const BatchItemDev *>(static_cast<char *>(workspace) + 256);
-  void *args[] = {&hdr, &items};
-  e = hipLaunchKernel(fn, dim3(ctas), dim3(kBatchThreads), args, lds, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
+  for (const BatchLaunch &l : ls) {
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, l.fn, kBatchThreads, l.lds);
+    if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: occupancy query");
+    int ctas = std::max(1, ncu * std::max(per_cu, 1));
+    if (max_ctas > 0) ctas = std::min(ctas, (int)max_ctas);
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(static_cast<char *>(workspace) + l.hdr_off);
+    const BatchItemDev *its = reinterpret_cast<const BatchItemDev *>(static_cast<char *>(workspace) + l.items_off);
+    void *args[] = {&hdr, &its};
+    e = hipLaunchKernel(l.fn, dim3(ctas), dim3(kBatchThreads), args, l.lds, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
+  }
   return CB_OK;
 }
 

@@ -1,5 +1,5 @@
-// HIP kernels of libcb for gfx950 (MI355X): the persistent batched launch,
-// the two-level (P > 1) kernels, the standalone stencil, and the dispatch.
+// HIP kernels of libcb for gfx950 (MI355X): the two-level (P > 1) kernels,
+// the standalone stencil, and the dispatch to the line and batched kernels.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -10,50 +10,6 @@
 #include "line.h"
 
 namespace cb {
-
-// ------------------------------------------------------------------------
-// Persistent batched launch: the grid takes tiles from a device work queue
-// that spans the lines of many (grid, axis, plan) items of uneven sizes.
-// Every item runs with the fused stencil (an identity stencil for plain
-// solves), the general lane layout and its own tile shape.  A workgroup
-// leaves when the queue is exhausted; the last one to leave resets the queue
-// so the launch can be replayed (e.g. from a captured graph) without a
-// memset.
-// ------------------------------------------------------------------------
-template <int R, int M, typename T>
-__global__ __launch_bounds__(512) void k_batched(BatchHdr *hdr, const BatchItemDev *items) {
-  extern __shared__ double smem[];
-  __shared__ int64_t s_tile;
-  const int64_t total = hdr->total_tiles;
-  const int nitems = hdr->n_items;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&hdr->next_tile, 1ull);
-    __syncthreads();
-    const int64_t t = s_tile;
-    __syncthreads();
-    if (t >= total) break;
-    int lo = 0, hi = nitems - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
-    }
-    const BatchItemDev &it = items[lo];
-    if (it.mode == MODE_X)
-      line_tile<R, M, T, MODE_X, 3, false>(it.a, t - it.tile_begin, smem);
-    else
-      line_tile<R, M, T, MODE_S, 3, false>(it.a, t - it.tile_begin, smem);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&hdr->done, 1u);
-    if (prev == gridDim.x - 1) {
-      atomicExch(&hdr->next_tile, 0ull);
-      atomicExch(&hdr->done, 0u);
-      __threadfence();
-    }
-  }
-}
 
 // ------------------------------------------------------------------------
 // Lines split over P > 1 workgroup partitions (Sec. 3-4 with workgroups as
@@ -433,16 +389,19 @@ const WgKernel *find_wg_kernel(int R, int M, int mode, int Q) {
 
 const void *stencil_kernel() { return (const void *)&k_stencil; }
 
-#define CB_BATCH_INST(R, M, T) {R, M, sizeof(T) == 8 ? 0 : 1, (const void *)&k_batched<R, M, T>}
-static const BatchKernel kBatchKernels[] = {
-    CB_BATCH_INST(1, 8, double), CB_BATCH_INST(2, 8, double), CB_BATCH_INST(1, 8, float), CB_BATCH_INST(2, 8, float),
-    CB_BATCH_INST(1, 16, double), CB_BATCH_INST(2, 16, double), CB_BATCH_INST(1, 16, float),
-    CB_BATCH_INST(2, 16, float),
-};
-
-const void *find_batch_kernel(int R, int M, int fp32) {
-  for (const auto &k : kBatchKernels)
-    if (k.R == R && k.M == M && k.fp32 == fp32) return k.fn;
+const void *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu) {
+  int cnt = 0;
+  const BatchKernel *t = nullptr;
+  switch (M) {
+    case 4: t = batch_table_m4(&cnt); break;
+    case 6: t = batch_table_m6(&cnt); break;
+    case 8: t = batch_table_m8(&cnt); break;
+    case 12: t = batch_table_m12(&cnt); break;
+    case 16: t = batch_table_m16(&cnt); break;
+    default: return nullptr;
+  }
+  for (int i = 0; i < cnt; ++i)
+    if (t[i].R == R && t[i].M == M && t[i].fp32 == fp32 && t[i].uni == uni && t[i].ilu == ilu) return t[i].fn;
   return nullptr;
 }
 

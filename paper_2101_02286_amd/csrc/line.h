@@ -19,7 +19,8 @@ constexpr int line_max_threads() {
 }
 
 // Exchange region size (doubles per thread and region): the halo exchange
-// carries 2Q values, the refinement residual 2r.
+// carries 2Q values, the refinement residual and the lane reduction 2r.
+// Staged unit-stride launches use 2r (their halo comes from the LDS tile).
 template <int R, int Q, int MODE>
 constexpr int line_region() {
   return 2 * Q > 2 * R ? 2 * Q : 2 * R;
@@ -51,7 +52,11 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     p.l = p.tid >> p.lgW;
     p.li = p.tid & (p.W - 1);
   }
-  Xchg xc{smem, RS, (int)blockDim.x, 0, a.block_sync != 0};
+  // staged unit-stride lines take their stencil halo from the tile, so their
+  // exchange regions only carry the 2r values of the lane reduction
+  const bool staged = MODE == MODE_X && a.stage_x;
+  const int RSr = staged ? 2 * R : RS;
+  Xchg xc{smem, RSr, (int)blockDim.x, 0, a.block_sync != 0};
   const SegDev &sg = a.seg;
   const int nrow = sg.S;  // line length (the whole line is this plan's one segment)
   const int64_t line = tile * p.W + p.li;
@@ -83,7 +88,6 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   // one pad word follows every M words, so each lane's M contiguous rows are
   // read back without bank conflicts.
   double *tb = nullptr;
-  const bool staged = MODE == MODE_X && a.stage_x;
   if (staged) tb = smem + a.stage_off + (size_t)p.li * a.stage_pitch;
   double b64[M];
   if (staged) {
@@ -152,7 +156,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   // general layouts: the lanes read different coefficient blocks, staged in LDS
   T *cl = nullptr;
   if (!UNI && a.coef_lds) {
-    cl = reinterpret_cast<T *>(smem + (size_t)2 * RS * blockDim.x);
+    cl = reinterpret_cast<T *>(smem + (size_t)2 * RSr * blockDim.x);
     stage_coef<T>(sg, cl, p.tid, blockDim.x);
   }
   auto solve = [&](T(&v)[M]) {
@@ -239,6 +243,55 @@ __global__ __launch_bounds__((line_max_threads<M, T, UNI>())) void k_line(const 
 }
 
 
+// ------------------------------------------------------------------------
+// Persistent batched launch: the grid takes tiles from a device work queue
+// that spans the lines of many (grid, axis, plan) items of uneven sizes, all
+// of one kernel class (r, rows per lane, arithmetic, lane layout, interior
+// solve).  Every item runs with the fused stencil (an identity stencil for
+// plain solves) and its own tile shape.  A workgroup leaves when the queue is
+// exhausted; the last one to leave resets the queue so the launch can be
+// replayed (e.g. from a captured graph) without a memset.
+// ------------------------------------------------------------------------
+template <int R, int M, typename T, bool UNI, bool ILU>
+__global__ __launch_bounds__(kBatchThreads) void k_batched(BatchHdr *hdr, const BatchItemDev *items) {
+  extern __shared__ double smem[];
+  __shared__ int64_t s_tile;
+  const int64_t total = hdr->total_tiles;
+  const int nitems = hdr->n_items;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&hdr->next_tile, 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= total) break;
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchItemDev &it = items[lo];
+    if (it.mode == MODE_X)
+      line_tile<R, M, T, MODE_X, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
+    else
+      line_tile<R, M, T, MODE_S, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&hdr->done, 1u);
+    if (prev == gridDim.x - 1) {
+      atomicExch(&hdr->next_tile, 0ull);
+      atomicExch(&hdr->done, 0u);
+      __threadfence();
+    }
+  }
+}
+
+#define CB_BATCH_INST(R, M, T, UNI, ILU) \
+  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, (const void *)&k_batched<R, M, T, UNI, ILU>}
+#define CB_BATCH_T(R, M, UNI, ILU) CB_BATCH_INST(R, M, double, UNI, ILU), CB_BATCH_INST(R, M, float, UNI, ILU)
+#define CB_BATCH_R(M, UNI, ILU) CB_BATCH_T(1, M, UNI, ILU), CB_BATCH_T(2, M, UNI, ILU)
+
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI, ILU) \
   {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<M, T, UNI>(), \
    (const void *)&k_line<R, M, T, MODE, Q, UNI, ILU>}
@@ -249,11 +302,16 @@ __global__ __launch_bounds__((line_max_threads<M, T, UNI>())) void k_line(const 
 #define CB_LINE_T(R, M, UNI, ILU) CB_LINE_MODE(R, M, double, UNI, ILU), CB_LINE_MODE(R, M, float, UNI, ILU)
 #define CB_LINE_R(M, UNI, ILU) CB_LINE_T(1, M, UNI, ILU), CB_LINE_T(2, M, UNI, ILU)
 
-// Per-M instance tables (defined in lines_m<M>.hip).
+// Per-M instance tables of the line and batched kernels (lines_m<M>.hip).
 const LineKernel *line_table_m4(int *count);
 const LineKernel *line_table_m6(int *count);
 const LineKernel *line_table_m8(int *count);
 const LineKernel *line_table_m12(int *count);
 const LineKernel *line_table_m16(int *count);
+const BatchKernel *batch_table_m4(int *count);
+const BatchKernel *batch_table_m6(int *count);
+const BatchKernel *batch_table_m8(int *count);
+const BatchKernel *batch_table_m12(int *count);
+const BatchKernel *batch_table_m16(int *count);
 
 }  // namespace cb

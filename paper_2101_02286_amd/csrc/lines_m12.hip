@@ -10,4 +10,11 @@ const LineKernel *line_table_m12(int *count) {
   return kTable;
 }
 
+static const BatchKernel kBatch[] = {CB_BATCH_R(12, true, false), CB_BATCH_R(12, true, true)};
+
+const BatchKernel *batch_table_m12(int *count) {
+  *count = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
+  return kBatch;
+}
+
 }  // namespace cb

@@ -11,4 +11,11 @@ const LineKernel *line_table_m16(int *count) {
   return kTable;
 }
 
+static const BatchKernel kBatch[] = {CB_BATCH_R(16, true, false), CB_BATCH_R(16, false, false), CB_BATCH_R(16, true, true), CB_BATCH_R(16, false, true)};
+
+const BatchKernel *batch_table_m16(int *count) {
+  *count = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
+  return kBatch;
+}
+
 }  // namespace cb

@@ -11,4 +11,11 @@ const LineKernel *line_table_m8(int *count) {
   return kTable;
 }
 
+static const BatchKernel kBatch[] = {CB_BATCH_R(8, true, false), CB_BATCH_R(8, false, false), CB_BATCH_R(8, true, true), CB_BATCH_R(8, false, true)};
+
+const BatchKernel *batch_table_m8(int *count) {
+  *count = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
+  return kBatch;
+}
+
 }  // namespace cb

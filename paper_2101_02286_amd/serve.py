@@ -161,7 +161,7 @@ def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_point
 class GpuExecutor:
     """Runs request groups as one persistent batched launch per stream slot."""
 
-    def __init__(self, slots=4, precision="fp32_refine", refine_iters=2, rows_per_lane=8, device="cuda:0",
+    def __init__(self, slots=4, precision="fp32_refine", refine_iters=2, rows_per_lane=0, device="cuda:0",
                  on_result=None):
         import torch
         from . import cb
@@ -190,7 +190,9 @@ class GpuExecutor:
         return self.plans[key], self.stencils[key]
 
     def group_key(self, r):
-        return (2 if r.scheme == "penta10" else 1)
+        # a batched launch takes any mix of plans (one persistent kernel per
+        # kernel class), so every request may join every batch
+        return 0
 
     def alloc(self, r):
         torch = self.torch

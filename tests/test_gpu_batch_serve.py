@@ -87,6 +87,51 @@ def test_batched_solve_items_and_penta(gpu):
         assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
 
 
+def test_mixed_plans_one_batch(gpu):
+    """Items of different schemes, precisions, lane layouts (uniform, ragged,
+    eliminated interiors) and axes in one batch: each matches the oracle and is
+    bitwise equal to the same item computed by a single call."""
+    cases = [  # (bands, n, precision, refine, per_row, axis, fused)
+        (TRI, 64, "fp64", 0, False, 0, True), (TRI, 96, "fp64", 0, False, 1, True),
+        (PENTA, 128, "fp32_refine", 3, False, 2, True), (TRI, 613, "fp64", 0, False, 0, False),
+        (PENTA, 384, "fp64", 0, False, 1, False), (TRI, 256, "fp32_refine", 2, False, 2, False),
+        (TRI, 200, "fp64", 0, True, 0, False), (PENTA, 512, "fp64", 0, False, 0, True),
+    ]
+    items, singles, refs = [], [], []
+    rng = np.random.default_rng(5)
+    for k, (bands, n, prec, it, per_row, axis, fused) in enumerate(cases):
+        shape = [7, 5]
+        shape.insert(axis, n)
+        shape = (shape[2], shape[1], shape[0])
+        if per_row:
+            bd = np.tile(np.asarray(bands, dtype=np.float64), (n, 1))
+            bd[:, 1] += rng.uniform(0.0, 0.5, n)  # stays diagonally dominant
+            plan = cb.Plan(bd, n, per_row=True, precision=prec, refine_iters=it)
+        else:
+            bd = bands
+            plan = cb.Plan(bands, n, precision=prec, refine_iters=it)
+        if fused:
+            f, _ = synth.random_modes(shape, seed=k)
+            lo, c = stencil_for("tri6" if bands is TRI else "penta10", n)
+            st = cb.Stencil(lo, c)
+            refs.append(oracle.apply_axis(f.numpy(), axis, bands, lo, c))
+            fd = f.to(gpu)
+            singles.append(cb.apply_derivative(plan, st, fd, axis))
+        else:
+            b = synth.random_uniform(shape, seed=k)
+            st = None
+            refs.append(oracle.solve_axis(b.numpy(), axis, bd, per_row=per_row))
+            fd = b.to(gpu)
+            singles.append(cb.solve(plan, fd, axis))
+        items.append((plan, st, fd, torch.empty_like(fd), axis))
+    launch(batch(items), max_ctas=11)
+    torch.cuda.synchronize()
+    for (plan, st, fd, out, axis), single, ref in zip(items, singles, refs):
+        got = out.cpu().numpy()
+        assert relerr(got, ref) <= 1e-12
+        assert np.array_equal(got, single.cpu().numpy())
+
+
 def test_batch_with_empty_items(gpu):
     """Items with no lines (first, middle, last) take no tiles; the others are solved."""
     plan = cb.Plan(TRI, 64, rows_per_lane=8)
