@@ -281,8 +281,19 @@ def mode_batched(args):
         dur, wall = _time_launches(launch, args.steps, args.warmup, stream)
         dof = sum(f.numel() for f in fields) * 3
         ms = float(dur.mean())
+        # the same launches captured once in a HIP graph and replayed
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=gs):
+            cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), 0,
+                                               cb.ctypes.c_void_p(gs.cuda_stream)))
+        torch.cuda.synchronize()
+        gdur, _ = _time_launches(g.replay, args.steps, args.warmup, torch.cuda.current_stream())
+        gms = float(gdur.mean())
         out[prec] = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
                      "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1), "items": len(items),
+                     "graph_replay_ms": round(gms, 4), "graph_replay_gdofs": round(dof / (gms * 1e-3) / 1e9, 2),
                      "outputs": [it[3] for it in items]}
     # accuracy of the FP32+refinement outputs against the FP64 outputs
     worst = 0.0
@@ -296,17 +307,21 @@ def mode_batched(args):
 def mode_serve(args):
     """Poisson request stream served with continuous batching (FP32+refinement)."""
     from paper_2101_02286_amd.serve import GpuExecutor, Server, poisson_requests
-    res = []
-    for rate in args.rates:
+    def run(rate, precision):
         reqs = poisson_requests(args.requests, rate_hz=rate, seed=11, max_points=args.max_points)
-        ex = GpuExecutor(slots=4)
+        ex = GpuExecutor(slots=4, precision=precision)
         for r in reqs:  # factorise every plan before the clock starts
             ex.plan(r.scheme, r.n)
         srv = Server(ex, hbm_budget=args.budget_gb * (1 << 30), slots=4, max_batch=16)
         st = srv.run(reqs)
         st["rate_hz"] = rate
-        res.append(st)
+        st["precision"] = precision
+        return st
+
+    res = [run(rate, "fp32_refine") for rate in args.rates]
+    fp64 = run(max(args.rates), "fp64")  # the same stream in plain FP64 at the highest rate
     return {"metric": "served p50/p99 latency and GDOF/s", "runs": res,
+            "saturation_gdofs": round(max(r["gdofs"] for r in res), 2), "fp64_at_highest_rate": fp64,
             "config": {"workload": "Poisson stream, sides log-uniform [32,1024], <= %.2g points, "
                                    "tri6/penta10, FP32+refinement(2)" % args.max_points}}
 
@@ -327,7 +342,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", default="headline",
                     choices=["headline", "two_level", "penta_z", "batched", "serve", "copy"])
-    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 800.0])
+    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 800.0, 3200.0, 1e9],
+                    help="Poisson arrival rates (requests/s); a huge rate = all requests at once (saturation)")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--max-points", type=float, default=1.5e8)
     ap.add_argument("--budget-gb", type=float, default=32.0)

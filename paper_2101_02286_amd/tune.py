@@ -1,6 +1,8 @@
 """Autotuner for the line-solver launch shape.
 
 For one (bands, n, precision, grid shape, axis) it times every valid choice of
+  * partitions    -- workgroups per line (the two-level split of Sec. 3-4 with
+    workgroups as partitions; FP64 lines of 1024 rows or more),
   * rows_per_lane -- where the reduction switches from registers (generalized
     PCR inside a lane, ceil(log2(rows_per_lane - r)) levels) to LDS (block
     PCR across lanes, log2(lanes) levels),
@@ -30,8 +32,22 @@ def _key(bands, n, precision, shape, axis, fused):
                                         "fused" if fused else "solve", ",".join("%.17g" % b for b in bands))
 
 
+PARTS = (2, 4, 8, 16)
+
+
 def candidates(bands, n, precision):
     out = []
+    if precision == "fp64" and n >= 1024:
+        for P in PARTS:
+            for rpl in (8, 16):
+                try:
+                    cb.Plan(bands, n, partitions=P, rows_per_lane=rpl, host_only=True).close()
+                except cb.CbError:
+                    continue
+                for w in (0, 2, 4, 8):
+                    for xs in (1, 2):
+                        out.append(dict(partitions=P, rows_per_lane=rpl, lines_per_wg=w, block_barriers=0,
+                                        x_staging=xs, interior=1))
     for rpl in ROWS:
         try:
             p = cb.Plan(bands, n, precision=precision, rows_per_lane=rpl, host_only=True)
@@ -45,8 +61,8 @@ def candidates(bands, n, precision):
             for bb in (0, 1):
                 for xs in (1, 2):
                     for it in ((1, 2) if rpl in (8, 12, 16) else (1,)):
-                        out.append(dict(rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb, x_staging=xs,
-                                        interior=it))
+                        out.append(dict(partitions=1, rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb,
+                                        x_staging=xs, interior=it))
     return out
 
 
@@ -99,7 +115,8 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
         table.append(dict(c, ms=ms))
         p.close()
     best = min(table, key=lambda r: r["ms"])
-    best = {k: best[k] for k in ("rows_per_lane", "lines_per_wg", "block_barriers", "x_staging", "interior")}
+    best = {k: best[k] for k in ("partitions", "rows_per_lane", "lines_per_wg", "block_barriers", "x_staging",
+                                 "interior")}
     if cache:
         db[key] = {"best": best, "table": table}
         os.makedirs(os.path.dirname(cache), exist_ok=True)

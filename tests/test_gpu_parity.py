@@ -115,12 +115,13 @@ def test_solve_in_place_and_strided_view(gpu):
 @pytest.mark.parametrize("P", [2, 3, 5, 16])
 @pytest.mark.parametrize("bands", ["tri", "penta"])
 @pytest.mark.parametrize("axis", [0, 2])
-def test_partitioned_lines(gpu, P, bands, axis):
+@pytest.mark.parametrize("xs", [1, 2])
+def test_partitioned_lines(gpu, P, bands, axis, xs):
     bd = TRI if bands == "tri" else PENTA
     n = 64 * P + 7
     shape = shape_with(axis, n, other=(6, 5))
     b = synth.random_uniform(shape, seed=P)
-    plan = cb.Plan(bd, n, partitions=P)
+    plan = cb.Plan(bd, n, partitions=P, x_staging=xs, lines_per_wg=2 if xs == 1 else 0)
     x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
     ref = oracle.solve_axis(b.numpy(), axis, bd)
     assert relerr(x, ref) <= 1e-12
@@ -251,12 +252,14 @@ def test_c3b_512_penta_z_full_size_sampled(gpu):
 
 @pytest.mark.parametrize("P", [4, 7])
 @pytest.mark.parametrize("axis", [0, 1])
-def test_partitioned_fused_derivative(gpu, P, axis):
+@pytest.mark.parametrize("xs", [1, 2])
+def test_partitioned_fused_derivative(gpu, P, axis, xs):
+    """Partitioned lines with the fused stencil; unit-stride rows direct (1) or staged (2)."""
     n = 96 * P
     shape = shape_with(axis, n, other=(5, 6))
     f, _ = synth.random_modes(shape, seed=P + axis)
     lo, c = deriv_stencil(schemes.DERIV10, n)
-    plan = cb.Plan(PENTA, n, partitions=P)
+    plan = cb.Plan(PENTA, n, partitions=P, x_staging=xs)
     out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
     ref = oracle.apply_axis(f.numpy(), axis, PENTA, lo, c)
     assert relerr(out, ref) <= 1e-12

@@ -195,3 +195,14 @@ def test_interior_elimination_rejected_where_unsupported():
         cb.Plan([1 / 3, 1, 1 / 3], 512, rows_per_lane=4, interior=2, host_only=True)
     with pytest.raises(cb.CbError):
         cb.Plan([1 / 3, 1, 1 / 3], 8192, partitions=16, interior=2, host_only=True)
+
+
+def test_tuner_searches_partition_counts_for_long_lines():
+    from paper_2101_02286_amd import tune
+    c = tune.candidates([1 / 3, 1.0, 1 / 3], 8192, "fp64")
+    parts = {x["partitions"] for x in c}
+    assert {2, 4, 8, 16} <= parts
+    for x in c:  # every candidate builds
+        cb.Plan([1 / 3, 1.0, 1 / 3], 8192, host_only=True, **x).close()
+    assert {x["partitions"] for x in tune.candidates([1 / 3, 1.0, 1 / 3], 512, "fp64")} == {1}
+    assert {x["partitions"] for x in tune.candidates([1 / 3, 1.0, 1 / 3], 8192, "fp32_refine")} == {1}
