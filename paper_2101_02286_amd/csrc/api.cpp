@@ -304,9 +304,11 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   int smax = 0;
   for (const SegPlan &sp : p.segs) smax = std::max(smax, sp.S);
   const int64_t pitch = stage_x ? smax + smax / p.M + 1 : 0;
-  auto lds_c_of = [&](int nt) {
-    return ((size_t)nt * 2 * RSw + (size_t)2 * (nt / L) * p.P * p.R + extra + (size_t)(nt / L) * pitch) * 8;
-  };
+  auto lds_c_of = [&](int nt) { return ((size_t)nt * 2 * RSw + extra + (size_t)(nt / L) * pitch) * 8; };
+  // phase B: one thread per (line, partition), 256-thread blocks
+  const int NTB = 256, WB = std::max(1, NTB / p.P);
+  const size_t lds_b = (size_t)2 * WB * p.P * p.R * sizeof(double);
+  if (lds_b > 65536) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
   while (NT > L && lds_c_of(NT) > 65536) NT /= 2;
   if (lds_c_of(NT) > 65536) return fail(CB_ERR_UNSUPPORTED, "partition too long for one workgroup");
   const int W = NT / L;
@@ -328,7 +330,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.nphase = p.prog.nphase;
   a.coef_lds = coef_lds ? 1 : 0;
   a.coef_off_a = (int64_t)NT * 2 * RSw;
-  a.coef_off_c = a.coef_off_a + (int64_t)2 * W * p.P * p.R;
+  a.coef_off_c = a.coef_off_a;
   a.stage_x = stage_x ? 1 : 0;
   a.stage_off_a = a.coef_off_a + (int64_t)extra;
   a.stage_off_c = a.coef_off_c + (int64_t)extra;
@@ -356,6 +358,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const size_t lds_a = ((size_t)a.stage_off_a + (size_t)W * pitch) * sizeof(double);
   const size_t lds_c = ((size_t)a.stage_off_c + (size_t)W * pitch) * sizeof(double);
   e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
+  if (e == hipSuccess)
+    e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
   hipError_t e2 = hipFreeAsync(scratch, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");

@@ -16,10 +16,10 @@ namespace cb {
 // partitions).  Phase A: y_i = D_i^{-1} b_i on each partition; the interface
 // RHS b~_i and the first/last R rows of y_i go to a small scratch array (the
 // only data a partition shares, Sec. 4 on the sparsity of L~ and U~).
-// Phase C: every workgroup of a line assembles b^ (Eq. (21)), solves the
-// P-block reduced system (Algorithm 1's level loop with detach/reattach,
-// precomputed as a program of phases), recomputes y_i and back-substitutes
-// (Eq. (22)).
+// Phase B: per line, b^ (Eq. (21)) and the P-block reduced system
+// (Algorithm 1's level loop with detach/reattach, precomputed as a program of
+// phases).  Phase C: each partition re-solves its interior with the
+// interface values as right-hand-side couplings (Eq. (9)) and stores.
 // ------------------------------------------------------------------------
 template <int R, int M, int MODE>
 __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &line, bool &active,
@@ -213,23 +213,22 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   }
 }
 
-template <int R, int M, int MODE, int Q>
-__global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
+// Phase B: the P-block reduced system of each line, solved once.  Every
+// thread owns one (line, partition) pair: it assembles b^_i (Eq. (21)) from
+// the scratch values of its partition and the previous one, then the
+// precomputed program of Algorithm 1 (block-PCR levels with detach/reattach
+// for any P, the final folded solve) runs in LDS; x~_i replaces b~_i in the
+// scratch array.
+template <int R>
+__global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
   extern __shared__ double smem[];
-  constexpr int RS = Q > R ? 2 * Q : 2 * R;
-  LanePos p;
-  int64_t line, base;
-  bool active;
-  wg_setup<R, M, MODE>(a, p, line, active, base);
-  const int P = a.P, part = blockIdx.y, NT = blockDim.x;
-  // reduced-system state in LDS: two buffers of [W][P][R], after the lane
-  // exchange area
-  double *xr0 = smem + (size_t)NT * 2 * RS;
-  double *xr1 = xr0 + (size_t)p.W * P * R;
-  const int64_t tile0 = (int64_t)blockIdx.x * p.W;
-  for (int idx = p.tid; idx < p.W * P; idx += NT) {
+  const int P = a.P, NT = blockDim.x;
+  const int WB = NT / P > 0 ? NT / P : 1;  // lines per block
+  double *cur = smem, *nxt = smem + (size_t)WB * P * R;
+  const int64_t line0 = (int64_t)blockIdx.x * WB;
+  for (int idx = threadIdx.x; idx < WB * P; idx += NT) {
     const int li = idx / P, j = idx % P;
-    const int64_t ln = tile0 + li;
+    const int64_t ln = line0 + li;
     double bh[R];
     if (ln < a.nlines) {
       const double *sj = a.scratch + (ln * P + j) * 3 * R;
@@ -247,13 +246,12 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
       for (int r = 0; r < R; ++r) bh[r] = 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) xr0[(li * P + j) * R + r] = bh[r];
+    for (int r = 0; r < R; ++r) cur[(li * P + j) * R + r] = bh[r];
   }
   __syncthreads();
-  double *cur = xr0, *nxt = xr1;
   for (int ph = 0; ph < a.nphase; ++ph) {
     const int *ro = a.row_off + ph * (P + 1);
-    for (int idx = p.tid; idx < p.W * P; idx += NT) {
+    for (int idx = threadIdx.x; idx < WB * P; idx += NT) {
       const int li = idx / P, j = idx % P;
       const int t0 = ro[j], t1 = ro[j + 1];
       double acc[R];
@@ -280,11 +278,37 @@ __global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
     cur = nxt;
     nxt = tmp;
   }
-  double xi[R], xi1[R];
+  for (int idx = threadIdx.x; idx < WB * P; idx += NT) {
+    const int li = idx / P, j = idx % P;
+    const int64_t ln = line0 + li;
+    if (ln >= a.nlines) continue;
+    double *sj = a.scratch + (ln * P + j) * 3 * R;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    xi[r] = cur[(p.li * P + part) * R + r];
-    xi1[r] = cur[(p.li * P + (part + 1) % P) * R + r];
+    for (int r = 0; r < R; ++r) sj[r] = cur[(li * P + j) * R + r];
+  }
+}
+
+// Phase C: x_i = D_i^{-1}[b_i - L_i x~_i - U_i x~_{i+1}] (Eq. (9), equal to
+// the back-substitution of Eq. (22)) from the interface values of phase B.
+template <int R, int M, int MODE, int Q>
+__global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
+  extern __shared__ double smem[];
+  constexpr int RS = Q > R ? 2 * Q : 2 * R;
+  LanePos p;
+  int64_t line, base;
+  bool active;
+  wg_setup<R, M, MODE>(a, p, line, active, base);
+  const int P = a.P, part = blockIdx.y, NT = blockDim.x;
+  double xi[R], xi1[R];
+  {
+    const int64_t ln = active ? line : 0;
+    const double *s0 = a.scratch + (ln * P + part) * 3 * R;
+    const double *s1 = a.scratch + (ln * P + (part + 1) % P) * 3 * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xi[r] = s0[r];
+      xi1[r] = s1[r];
+    }
   }
   Xchg xc{smem, RS, NT, 0, true};
   double v[M];
@@ -373,8 +397,9 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
   return nullptr;
 }
 
-#define CB_WG_INST(R, M, MODE, Q) \
-  {R, M, MODE, Q, (const void *)&k_wg_a<R, M, MODE, Q>, (const void *)&k_wg_c<R, M, MODE, Q>}
+#define CB_WG_INST(R, M, MODE, Q)                                                                      \
+  {R, M, MODE, Q, (const void *)&k_wg_a<R, M, MODE, Q>, (const void *)&k_wg_b<R>,                       \
+   (const void *)&k_wg_c<R, M, MODE, Q>}
 #define CB_WG_Q(R, M, MODE) CB_WG_INST(R, M, MODE, 0), CB_WG_INST(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {
     CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),

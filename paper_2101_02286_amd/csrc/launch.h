@@ -80,7 +80,7 @@ struct LineKernel {
 };
 struct WgKernel {
   int R, M, mode, Q;
-  const void *fn_a, *fn_c;
+  const void *fn_a, *fn_b, *fn_c;  // phases A (interiors), B (reduced system), C (back-substitution)
 };
 
 // Persistent batched launch: queue header and one work-table entry per item.
