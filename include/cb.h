@@ -88,13 +88,14 @@ typedef struct {
   int32_t block_barriers; /* 0: lane exchanges of a line that lies inside one
                              wavefront use wavefront-local ordering only;
                              1: always workgroup barriers */
-  int32_t x_staging;      /* unit-stride lines: 0 automatic (= 2), 1 lanes load
+  int32_t x_staging;      /* unit-stride lines: 0 automatic (2 when one line's
+                             tile fits in 64 KB of LDS, else 1), 1 lanes load
                              their rows directly, 2 through a coalesced LDS tile */
   int32_t interior;       /* solve of each lane's interior block D_l: 0 automatic
-                             (1 for unit-stride launches; for strided ones 2
-                             where available), 1 generalized PCR (Sec. 2),
-                             2 banded elimination in registers
-                             (rows_per_lane 8/12/16) */
+                             (unit-stride launches: 1 on uniform lanes, 2 on
+                             general ones; strided launches: 2 where
+                             available), 1 generalized PCR (Sec. 2), 2 banded
+                             elimination in registers (rows_per_lane 8/12/16) */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +

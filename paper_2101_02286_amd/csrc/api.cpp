@@ -37,6 +37,24 @@ std::map<void *, std::vector<BatchLaunch>> g_batch_sel;
 constexpr size_t kBatchHdrBytes = 64;
 size_t batch_items_offset(size_t n_items) { return (std::max<size_t>(n_items, 1) * kBatchHdrBytes + 255) / 256 * 256; }
 
+// LDS a workgroup may allocate on the current device (160 KB on gfx950),
+// queried once per device; 64 KB if the query fails.
+size_t lds_cap() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  size_t cap = 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    cap = (size_t)v;
+  cache[dev] = cap;
+  return cap;
+}
+
 cb_status fail(cb_status s, const std::string &m) {
   g_err = m;
   return s;
@@ -205,10 +223,15 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
   const bool fp32 = p.precision != CB_FP64;
-  // MODE_X needs unit row stride; the vectorised direct loads of uniform
-  // layouts (no LDS tile) also need 16-byte aligned line starts.
+  // MODE_X needs unit row stride.  Its lines go through an LDS tile unless
+  // asked otherwise or, automatically, when one line's tile would exceed
+  // 64 KB (long lines: the tile would cost occupancy).  The vectorised direct
+  // loads of uniform layouts also need 16-byte aligned line starts.
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
-  if (mode == MODE_X && uni && p.desc.x_staging == 1) {
+  const int64_t tile1 = (g.n + g.n / sp.M + 1 + (int64_t)sp.L * 4 * p.R) * (int64_t)sizeof(double);
+  const bool stage_x =
+      mode == MODE_X && (p.desc.x_staging == 2 || (p.desc.x_staging == 0 && tile1 <= 65536));
+  if (mode == MODE_X && uni && !stage_x) {
     const bool al = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
                     (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
     if (!al) mode = MODE_S;
@@ -224,13 +247,13 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   } else if (mode == MODE_X) {
     // staged unit-stride lines: one line per workgroup measured best (512^3);
     // direct loads: 512-thread workgroups
-    W = (p.desc.x_staging != 1) ? 1 : std::max(1, 512 / L);
+    W = stage_x ? 1 : std::max(1, 512 / L);
   } else {
     W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread (2r when the
-  // unit-stride tile is staged: its halo comes from the tile), at most 64 KB
-  const bool stage_x = mode == MODE_X && p.desc.x_staging != 1;
+  // unit-stride tile is staged: its halo comes from the tile), within the
+  // device's LDS per workgroup
   const int RS = stage_x ? 2 * p.R : std::max(2 * Q, 2 * p.R);
   // general layouts stage their coefficient blocks in LDS when they are small
   const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp32 ? 4 : 8);
@@ -242,9 +265,10 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   auto lds_of = [&](int w) {
     return ((size_t)w * L * 2 * RS + coef_dbl + (size_t)w * pitch) * sizeof(double);
   };
-  while (W > 1 && (lds_of(W) > 65536 || W * L > lk->max_threads)) W /= 2;
+  const size_t cap = lds_cap();
+  while (W > 1 && (lds_of(W) > cap || W * L > lk->max_threads)) W /= 2;
   const int NT = W * L;
-  if (lds_of(W) > 65536 || NT > lk->max_threads)
+  if (lds_of(W) > cap || NT > lk->max_threads)
     return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup of this kernel");
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
   // one wavefront and its exchanges need no workgroup barrier
@@ -293,7 +317,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
   NT = std::min(std::max(NT, L), 1024);
-  // keep the LDS of phase C (lane exchange + reduced-system state) within 64 KB
+  // keep the LDS of phases A and C (lane exchange, coefficients, tile) within
+  // the device's LDS per workgroup
   const int RSw = 2 * std::max(p.R, Q);
   size_t coef_doubles = 0;
   for (const SegPlan &sp : p.segs) coef_doubles = std::max(coef_doubles, (size_t)sp.ntypes * sp.block);
@@ -308,9 +333,10 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // phase B: one thread per (line, partition), 256-thread blocks
   const int NTB = 256, WB = std::max(1, NTB / p.P);
   const size_t lds_b = (size_t)2 * WB * p.P * p.R * sizeof(double);
-  if (lds_b > 65536) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
-  while (NT > L && lds_c_of(NT) > 65536) NT /= 2;
-  if (lds_c_of(NT) > 65536) return fail(CB_ERR_UNSUPPORTED, "partition too long for one workgroup");
+  const size_t cap = lds_cap();
+  if (lds_b > cap) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
+  while (NT > L && lds_c_of(NT) > cap) NT /= 2;
+  if (lds_c_of(NT) > cap) return fail(CB_ERR_UNSUPPORTED, "partition too long for one workgroup");
   const int W = NT / L;
   WgArgs a;
   std::memset(&a, 0, sizeof(a));

@@ -104,6 +104,15 @@ __device__ __forceinline__ T select_idx(const T (&y)[N], int idx) {
   return r;
 }
 
+// Rows of lane l in a segment of S rows over L = 2^lgL lanes: the first
+// S mod L lanes hold one row more (the layout the plan builds), so a lane's
+// first row and row count follow without a table lookup.
+__device__ __forceinline__ void lane_rows(int S, int lgL, int l, int &start, int &m) {
+  const int base = S >> lgL, extra = S & ((1 << lgL) - 1);
+  start = l * base + (l < extra ? l : extra);
+  m = base + (l < extra ? 1 : 0);
+}
+
 // Where a lane's coefficient block is read from: the plan in global memory
 // through the constant address space (uniform plans: scalar loads), or a
 // copy staged in LDS (general plans, whose lanes read different blocks).

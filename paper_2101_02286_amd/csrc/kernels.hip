@@ -65,8 +65,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
                                                   const double (&xi)[R], const double (&xi1)[R]) {
   const SegDev &sg = a.segs[part];
   if (a.coef_lds) stage_coef<double>(sg, coef_lds, p.tid, blockDim.x);
-  start = sg.lane_start[p.l];
-  m = sg.lane_start[p.l + 1] - start;
+  lane_rows(sg.S, p.lgL, p.l, start, m);
   const int type = sg.lane_type[p.l];
   const int S = sg.S;
   const int64_t seg0 = a.wg_start[part] + R;  // first row of the interior block D_i

@@ -10,12 +10,14 @@
 
 namespace cb {
 
-// Workgroup size bound of a line-kernel instance: register-heavy instances
-// (FP32 reduction with FP64 refinement state, 12-16 rows per lane, or the
-// general lane layout) get up to 256 VGPRs by allowing at most 512 threads.
-template <int M, typename T, bool UNI>
+// Workgroup size bound of a line-kernel instance.  FP64 instances fit 128
+// VGPRs and allow 1024 threads, except general-layout unit-stride ones (LDS
+// tile plus per-lane coefficients); FP32 instances carry the FP64
+// refinement state beside the FP32 reduction and get up to 256 VGPRs by
+// allowing at most 512 threads.
+template <int M, typename T, int MODE, bool UNI>
 constexpr int line_max_threads() {
-  return (sizeof(T) == 4 || !UNI) ? 512 : 1024;
+  return sizeof(T) == 4 ? 512 : ((UNI || MODE == 1) ? 1024 : 512);
 }
 
 // Exchange region size (doubles per thread and region): the halo exchange
@@ -70,8 +72,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     m = M;
     start = p.l * M;
   } else {
-    start = sg.lane_start[p.l];
-    m = sg.lane_start[p.l + 1] - start;
+    lane_rows(sg.S, p.lgL, p.l, start, m);
     type = sg.lane_type[p.l];
   }
   const int64_t rs = MODE == MODE_X ? 1 : a.rs;
@@ -237,7 +238,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
 }
 
 template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU>
-__global__ __launch_bounds__((line_max_threads<M, T, UNI>())) void k_line(const LineArgs a) {
+__global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_line(const LineArgs a) {
   extern __shared__ double smem[];
   line_tile<R, M, T, MODE, Q, UNI, ILU>(a, (int64_t)blockIdx.x, smem);
 }
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(BatchHdr *hdr, const 
 #define CB_BATCH_R(M, UNI, ILU) CB_BATCH_T(1, M, UNI, ILU), CB_BATCH_T(2, M, UNI, ILU)
 
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI, ILU) \
-  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<M, T, UNI>(), \
+  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<M, T, MODE, UNI>(), \
    (const void *)&k_line<R, M, T, MODE, Q, UNI, ILU>}
 #define CB_LINE_Q(R, M, T, MODE, UNI, ILU)                                             \
   CB_LINE_INST(R, M, T, MODE, 0, UNI, ILU), CB_LINE_INST(R, M, T, MODE, 2, UNI, ILU), \

@@ -544,19 +544,21 @@ cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
 enum { PREF_X = 0, PREF_S = 1 };
 
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
-                 bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16) {
+                 bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16, int lcap = 1024) {
   static const int kUniMx[] = {8, 4, 6, 12, 16};
   static const int kUniMs[] = {16, 12, 8, 6, 4};
   const int *kUniM = pref == PREF_X ? kUniMx : kUniMs;
   if (allow_uniform) {
+    // first lines of at most 64 lanes in the preferred order, then longer
+    // lines with as few lanes as possible (fewer block-PCR levels)
     for (int pass = 0; pass < 2; ++pass)
       for (int mi = 0; mi < 5; ++mi) {
-        const int m = kUniM[mi];
+        const int m = pass == 0 ? kUniM[mi] : kUniMs[mi];
         if (M_req && m != M_req) continue;
         if (!M_req && m > m_max) continue;
         if (m < 2 * R || S % m) continue;
         const int l = S / m;
-        const int lmax = pass == 0 ? 64 : 1024;
+        const int lmax = pass == 0 ? 64 : lcap;
         if (!is_pow2(l) || l > lmax) continue;
         L = l;
         M = m;
@@ -565,9 +567,13 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
         return true;
       }
   }
+  // general layout (lanes of two sizes): unit-stride launches prefer 8 rows
+  // per lane, strided ones 16 (fewer lanes, so 16 lines share a workgroup)
   uniform = false;
   m_uni = 0;
-  M = M_req ? M_req : ((S + 7) / 8 <= 64 || m_max < 16 ? 8 : 16);
+  if (M_req) M = M_req;
+  else if (pref == PREF_S) M = m_max >= 16 ? 16 : 8;
+  else M = ((S + 7) / 8 <= 1024 || m_max < 16) ? 8 : 16;
   if (M != 8 && M != 16) return false;
   if (L_req > 0) {
     L = L_req;
@@ -576,7 +582,7 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
     while (L * M < S) L *= 2;
     while (L > 1 && S / L < 2 * R) L /= 2;
   }
-  if (L > 1024 || (S + L - 1) / L > M || S / L < 2 * R) return false;
+  if (L > lcap || (S + L - 1) / L > M || S / L < 2 * R) return false;
   return true;
 }
 
@@ -612,11 +618,12 @@ cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, do
 
 cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
                         const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
-                        std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16, int interior = 0) {
+                        std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16, int interior = 0,
+                        int lcap = 1024) {
   int L, M, m_uni;
   bool uni;
   if (!lane_layout(S, R, M_req, L, M, uni, m_uni, cyclic && !per_row_any && L_req == 0, L_req, pref,
-                   m_max)) {
+                   m_max, lcap)) {
     msg = "no lane layout for this segment length (rows_per_lane unsupported?)";
     return CB_ERR_UNSUPPORTED;
   }
@@ -631,15 +638,19 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   sp.uniform = uni;
   sp.m_uniform = m_uni;
   // interior solve: 0/1 generalized PCR, 2 elimination, 3 elimination where
-  // a kernel exists for it (8 or 16 rows per lane, or 12 on uniform lanes)
+  // a kernel exists for it (8 or 16 rows per lane, or 12 on uniform lanes),
+  // 4 elimination for general layouts only
   sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16)) ||
-                   (interior == 3 && (M == 8 || M == 16 || (M == 12 && uni)))
+                   (interior == 3 && (M == 8 || M == 16 || (M == 12 && uni))) ||
+                   (interior == 4 && !uni && (M == 8 || M == 16))
                ? 1
                : 0;
   if (interior == 2 && !sp.ilu) {
     msg = "interior elimination needs rows_per_lane 8, 12 or 16";
     return CB_ERR_UNSUPPORTED;
   }
+  // the first S mod L lanes hold one row more (the kernels recompute these
+  // starts from S and L, see lane_rows)
   std::vector<int> st(L + 1);
   const int base = S / L, extra = S % L;
   st[0] = 0;
@@ -778,10 +789,18 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     // segs[0]: layout for unit-stride launches; segs[seg_s]: for strided ones
     // the FP32 reduction keeps FP64 refinement state beside it: at most 8 rows
     // per lane unless asked for
-    const int m_max = d.precision == CB_FP64 ? 16 : 8;
+    // FP32 line kernels run at most 512 threads, so at most 512 lanes: long
+    // FP32 lines may use 16 rows per lane
+    const int m_max = d.precision == CB_FP64 || n > 8 * 512 ? 16 : 8;
+    const int lcap = d.precision == CB_FP64 ? 1024 : 512;
     p.segs.resize(1);
+    // unit-stride lines: generalized PCR interiors on uniform lanes,
+    // elimination on general ones (measured faster each), unless asked
     cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X,
-                                m_max, d.interior);
+                                m_max, d.interior ? d.interior : 4, lcap);
+    if (s != CB_OK && d.interior == 0)
+      s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X, m_max, 1,
+                        lcap);
     if (s != CB_OK) return s;
     p.seg_s = 0;
     if (!d.rows_per_lane) {
@@ -789,9 +808,9 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       // (fewer live registers per lane; PCR if a pivot vanishes)
       SegPlan alt;
       s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max,
-                        d.interior ? d.interior : 3);
+                        d.interior ? d.interior : 3, lcap);
       if (s != CB_OK && d.interior == 0)
-        s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, 1);
+        s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, 1, lcap);
       if (s != CB_OK) return s;
       if (alt.M != p.segs[0].M || alt.L != p.segs[0].L || alt.ilu != p.segs[0].ilu) {
         p.segs.push_back(std::move(alt));
@@ -823,6 +842,7 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   int M = d.rows_per_lane, Lg = 0;
   {
     const int Smax = base + (extra ? 1 : 0) - R;
+    if (!M) M = (Smax + 7) / 8 <= 64 ? 8 : 16;  // at most 64 lanes of 8 rows, else 16 rows
     int m_uni;
     bool uni;
     if (!lane_layout(Smax, R, M, Lg, M, uni, m_uni, false)) {
