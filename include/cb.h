@@ -160,9 +160,9 @@ typedef struct {
  * different plans -- run in persistent kernel launches that take line tiles
  * from device work queues: ONE launch per kernel class present in the batch
  * (a class is r, rows per lane, arithmetic, uniform or general lane layout,
- * and interior solve of the lane layout an item's row stride selects; a
- * batch of plans built alike for one scheme and precision is usually one or
- * two classes).  Every plan must have partitions = 1 and be cyclic when a
+ * interior solve and unit-stride or strided rows, as an item's plan and row
+ * stride select them; a batch of plans built alike for one scheme and
+ * precision is usually a few classes).  Every plan must have partitions = 1 and be cyclic when a
  * stencil is given; n, axis, grid, stencil, precision and refinement count
  * may differ between items.  Each line goes through the same arithmetic as
  * in a single cb_solve / cb_apply_derivative call with the same plan.

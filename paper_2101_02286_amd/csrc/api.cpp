@@ -28,6 +28,7 @@ thread_local std::string g_err;
 struct BatchLaunch {
   const void *fn;
   size_t hdr_off, items_off, lds;
+  int threads;
 };
 std::mutex g_batch_mu;
 std::map<void *, std::vector<BatchLaunch>> g_batch_sel;
@@ -530,6 +531,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     int R, M, fp;
     bool uni, ilu;
     const void *fn;
+    int threads;
     size_t lds;
     std::vector<int> members;
   };
@@ -559,17 +561,15 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     const SegPlan &sp = p.segs[si];
     const int fp = p.precision != CB_FP64;
     const bool uni = sp.uniform != 0, ilu = sp.ilu != 0;
-    const void *fn = find_batch_kernel(p.R, sp.M, fp, uni, ilu);
-    if (!fn) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: no batched kernel for an item's lane layout");
     const int L = sp.L;
-    if (L > kBatchThreads) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: line needs too many lanes");
-    const int W = kBatchThreads / L;
     // tile shape and LDS: unit-stride lines through an LDS tile when it fits
     // in 64 KB (halo from the tile, exchange regions of 2r values), else with
-    // direct loads; strided lines as W adjacent lines (128-byte segments)
+    // direct loads; strided lines as W adjacent lines per row segment.  Items
+    // of one kernel class and workgroup size share a launch; W = threads / L.
     const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp ? 4 : 8);
     const size_t coef_dbl_if = (coef_bytes + 7) / 8;
     const int RSs = std::max(6, 2 * p.R);  // stencil halo of +-3 rows
+    int W = 0;
     auto lds_bytes = [&](int RS, bool coef, int64_t pitch) {
       return ((size_t)W * L * 2 * RS + (coef ? coef_dbl_if : 0) + (size_t)W * pitch) * 8;
     };
@@ -577,21 +577,41 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     bool stage = false, coef_lds = false;
     int64_t pitch = 0;
     int RS = RSs;
+    const BatchKernel *bk = nullptr;
+    // workgroup size: 512 threads, or up to the instance's bound when a line
+    // needs more lanes (unit stride) or 16 strided lines would not fit
+    int nt = 0;
     if (mode == MODE_X) {
-      const int64_t pt = g.n + g.n / sp.M + 1;
-      if (lds_bytes(2 * p.R, false, pt) <= 65536) {
-        stage = true;
-        pitch = pt;
-        RS = 2 * p.R;
-      } else if (uni) {  // direct loads of a uniform layout use 16-byte vectors
-        const bool al = ((uintptr_t)it.in % 16 == 0) && ((uintptr_t)it.out % 16 == 0) &&
-                        (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
-        if (!al) mode = MODE_S;
+      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_X);
+      if (bk) nt = std::min(bk->threads, std::max(512, L));
+      if (bk && L <= nt) {
+        W = nt / L;
+        const int64_t pt = g.n + g.n / sp.M + 1;
+        if (lds_bytes(2 * p.R, false, pt) <= 65536) {
+          stage = true;
+          pitch = pt;
+          RS = 2 * p.R;
+        } else if (uni) {  // direct loads of a uniform layout use 16-byte vectors
+          const bool al = ((uintptr_t)it.in % 16 == 0) && ((uintptr_t)it.out % 16 == 0) &&
+                          (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
+          if (!al) mode = MODE_S;
+        }
+      } else {
+        mode = MODE_S;
       }
     }
-    coef_lds = !uni && coef_bytes <= 16384 && lds_bytes(RS, true, pitch) <= 65536;
+    if (mode == MODE_S) {
+      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_S);
+      if (bk) nt = std::min(bk->threads, std::max(512, 16 * L));
+      if (bk && L <= nt) W = nt / L;
+    }
+    if (!bk || W == 0)
+      return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: no batched kernel for an item's lane layout");
+    const void *fn = bk->fn;
+    const size_t cap = lds_cap();
+    coef_lds = !uni && coef_bytes <= 16384 && lds_bytes(RS, true, pitch) <= cap;
     const size_t lds = lds_bytes(RS, coef_lds, pitch);
-    if (lds > 65536) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: an item's tile exceeds 64 KB of LDS");
+    if (lds > cap) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: an item's tile exceeds the LDS of a workgroup");
     BatchItemDev &d = tab[i];
     std::memset(&d, 0, sizeof(d));
     LineArgs &a = d.a;
@@ -622,8 +642,8 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     d.mode = mode;
     ntiles[i] = (g.nlines + W - 1) / W;
     int c = 0;
-    while (c < (int)cls.size() && !(cls[c].fn == fn)) ++c;
-    if (c == (int)cls.size()) cls.push_back(Cls{p.R, sp.M, fp, uni, ilu, fn, 0, {}});
+    while (c < (int)cls.size() && !(cls[c].fn == fn && cls[c].threads == nt)) ++c;
+    if (c == (int)cls.size()) cls.push_back(Cls{p.R, sp.M, fp, uni, ilu, fn, nt, 0, {}});
     cls[c].lds = std::max(cls[c].lds, lds);
     cls[c].members.push_back(i);
     cls_of[i] = c;
@@ -651,7 +671,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     std::memcpy(host.data() + c * kBatchHdrBytes, &h, sizeof(h));
     launches.push_back({cls[c].fn, c * kBatchHdrBytes,
                         batch_items_offset(n_items) + (slot - cls[c].members.size()) * sizeof(BatchItemDev),
-                        cls[c].lds});
+                        cls[c].lds, cls[c].threads});
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, st);
@@ -677,14 +697,14 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
   for (const BatchLaunch &l : ls) {
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, l.fn, kBatchThreads, l.lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, l.fn, l.threads, l.lds);
     if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: occupancy query");
     int ctas = std::max(1, ncu * std::max(per_cu, 1));
     if (max_ctas > 0) ctas = std::min(ctas, (int)max_ctas);
     BatchHdr *hdr = reinterpret_cast<BatchHdr *>(static_cast<char *>(workspace) + l.hdr_off);
     const BatchItemDev *its = reinterpret_cast<const BatchItemDev *>(static_cast<char *>(workspace) + l.items_off);
     void *args[] = {&hdr, &its};
-    e = hipLaunchKernel(l.fn, dim3(ctas), dim3(kBatchThreads), args, l.lds, static_cast<hipStream_t>(stream));
+    e = hipLaunchKernel(l.fn, dim3(ctas), dim3(l.threads), args, l.lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
   }
   return CB_OK;

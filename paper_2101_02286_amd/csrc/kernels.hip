@@ -413,7 +413,7 @@ const WgKernel *find_wg_kernel(int R, int M, int mode, int Q) {
 
 const void *stencil_kernel() { return (const void *)&k_stencil; }
 
-const void *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu) {
+const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode) {
   int cnt = 0;
   const BatchKernel *t = nullptr;
   switch (M) {
@@ -425,7 +425,8 @@ const void *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu) {
     default: return nullptr;
   }
   for (int i = 0; i < cnt; ++i)
-    if (t[i].R == R && t[i].M == M && t[i].fp32 == fp32 && t[i].uni == uni && t[i].ilu == ilu) return t[i].fn;
+    if (t[i].R == R && t[i].M == M && t[i].fp32 == fp32 && t[i].uni == uni && t[i].ilu == ilu && t[i].mode == mode)
+      return &t[i];
   return nullptr;
 }
 

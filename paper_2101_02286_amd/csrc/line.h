@@ -248,13 +248,14 @@ __global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_line(
 // Persistent batched launch: the grid takes tiles from a device work queue
 // that spans the lines of many (grid, axis, plan) items of uneven sizes, all
 // of one kernel class (r, rows per lane, arithmetic, lane layout, interior
-// solve).  Every item runs with the fused stencil (an identity stencil for
+// solve, unit-stride or strided rows).  Every item runs with the fused stencil (an identity stencil for
 // plain solves) and its own tile shape.  A workgroup leaves when the queue is
 // exhausted; the last one to leave resets the queue so the launch can be
 // replayed (e.g. from a captured graph) without a memset.
 // ------------------------------------------------------------------------
-template <int R, int M, typename T, bool UNI, bool ILU>
-__global__ __launch_bounds__(kBatchThreads) void k_batched(BatchHdr *hdr, const BatchItemDev *items) {
+template <int R, int M, typename T, bool UNI, bool ILU, int MODE>
+__global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
+                                                                               const BatchItemDev *items) {
   extern __shared__ double smem[];
   __shared__ int64_t s_tile;
   const int64_t total = hdr->total_tiles;
@@ -271,10 +272,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(BatchHdr *hdr, const 
       if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
     }
     const BatchItemDev &it = items[lo];
-    if (it.mode == MODE_X)
-      line_tile<R, M, T, MODE_X, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
-    else
-      line_tile<R, M, T, MODE_S, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
+    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -288,9 +286,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched(BatchHdr *hdr, const 
   }
 }
 
-#define CB_BATCH_INST(R, M, T, UNI, ILU) \
-  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, (const void *)&k_batched<R, M, T, UNI, ILU>}
-#define CB_BATCH_T(R, M, UNI, ILU) CB_BATCH_INST(R, M, double, UNI, ILU), CB_BATCH_INST(R, M, float, UNI, ILU)
+#define CB_BATCH_INST(R, M, T, UNI, ILU, MODE)                                                 \
+  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, MODE, line_max_threads<M, T, MODE, UNI>(),          \
+   (const void *)&k_batched<R, M, T, UNI, ILU, MODE>}
+#define CB_BATCH_MODE(R, M, T, UNI, ILU) CB_BATCH_INST(R, M, T, UNI, ILU, MODE_X), CB_BATCH_INST(R, M, T, UNI, ILU, MODE_S)
+#define CB_BATCH_T(R, M, UNI, ILU) CB_BATCH_MODE(R, M, double, UNI, ILU), CB_BATCH_MODE(R, M, float, UNI, ILU)
 #define CB_BATCH_R(M, UNI, ILU) CB_BATCH_T(1, M, UNI, ILU), CB_BATCH_T(2, M, UNI, ILU)
 
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI, ILU) \
