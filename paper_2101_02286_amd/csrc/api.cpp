@@ -250,7 +250,8 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
     // direct loads: 512-thread workgroups
     W = stage_x ? 1 : std::max(1, 512 / L);
   } else {
-    W = std::max(1, std::min(16, 1024 / L));  // 16 adjacent lines: 128-byte row segments
+    // adjacent lines: 16 (128-byte row segments), 32 with 32 rows per lane
+    W = std::max(1, std::min(sp.M == 32 ? 32 : 16, 1024 / L));
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread (2r when the
   // unit-stride tile is staged: its halo comes from the tile), within the

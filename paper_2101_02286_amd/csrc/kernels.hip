@@ -387,6 +387,7 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
     case 8: t = line_table_m8(&cnt); break;
     case 12: t = line_table_m12(&cnt); break;
     case 16: t = line_table_m16(&cnt); break;
+    case 32: t = line_table_m32(&cnt); break;
     default: return nullptr;
   }
   for (int i = 0; i < cnt; ++i)
@@ -422,6 +423,7 @@ const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu,
     case 8: t = batch_table_m8(&cnt); break;
     case 12: t = batch_table_m12(&cnt); break;
     case 16: t = batch_table_m16(&cnt); break;
+    case 32: t = batch_table_m32(&cnt); break;
     default: return nullptr;
   }
   for (int i = 0; i < cnt; ++i)

@@ -309,10 +309,12 @@ const LineKernel *line_table_m6(int *count);
 const LineKernel *line_table_m8(int *count);
 const LineKernel *line_table_m12(int *count);
 const LineKernel *line_table_m16(int *count);
+const LineKernel *line_table_m32(int *count);
 const BatchKernel *batch_table_m4(int *count);
 const BatchKernel *batch_table_m6(int *count);
 const BatchKernel *batch_table_m8(int *count);
 const BatchKernel *batch_table_m12(int *count);
 const BatchKernel *batch_table_m16(int *count);
+const BatchKernel *batch_table_m32(int *count);
 
 }  // namespace cb

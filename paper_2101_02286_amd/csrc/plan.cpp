@@ -545,14 +545,14 @@ enum { PREF_X = 0, PREF_S = 1 };
 
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
                  bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16, int lcap = 1024) {
-  static const int kUniMx[] = {8, 4, 6, 12, 16};
-  static const int kUniMs[] = {16, 12, 8, 6, 4};
+  static const int kUniMx[] = {8, 4, 6, 12, 16, 32};
+  static const int kUniMs[] = {32, 16, 12, 8, 6, 4};
   const int *kUniM = pref == PREF_X ? kUniMx : kUniMs;
   if (allow_uniform) {
     // first lines of at most 64 lanes in the preferred order, then longer
     // lines with as few lanes as possible (fewer block-PCR levels)
     for (int pass = 0; pass < 2; ++pass)
-      for (int mi = 0; mi < 5; ++mi) {
+      for (int mi = 0; mi < 6; ++mi) {
         const int m = pass == 0 ? kUniM[mi] : kUniMs[mi];
         if (M_req && m != M_req) continue;
         if (!M_req && m > m_max) continue;
@@ -640,13 +640,18 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
   // interior solve: 0/1 generalized PCR, 2 elimination, 3 elimination where
   // a kernel exists for it (8 or 16 rows per lane, or 12 on uniform lanes),
   // 4 elimination for general layouts only
-  sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16)) ||
-                   (interior == 3 && (M == 8 || M == 16 || (M == 12 && uni))) ||
-                   (interior == 4 && !uni && (M == 8 || M == 16))
+  // 32 rows per lane (uniform FP64 lanes only) always eliminate
+  sp.ilu = (interior == 2 && (M == 8 || M == 12 || M == 16 || M == 32)) ||
+                   (interior == 3 && (M == 8 || M == 16 || ((M == 12 || M == 32) && uni))) ||
+                   (interior == 4 && !uni && (M == 8 || M == 16)) || (M == 32 && interior != 1)
                ? 1
                : 0;
   if (interior == 2 && !sp.ilu) {
-    msg = "interior elimination needs rows_per_lane 8, 12 or 16";
+    msg = "interior elimination needs rows_per_lane 8, 12, 16 or 32";
+    return CB_ERR_UNSUPPORTED;
+  }
+  if (M == 32 && (!uni || !sp.ilu)) {
+    msg = "32 rows per lane need uniform lanes and interior elimination";
     return CB_ERR_UNSUPPORTED;
   }
   // the first S mod L lanes hold one row more (the kernels recompute these
@@ -735,8 +740,8 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     return CB_ERR_INVALID_ARG;
   }
   if (d.rows_per_lane && d.rows_per_lane != 4 && d.rows_per_lane != 6 && d.rows_per_lane != 8 &&
-      d.rows_per_lane != 12 && d.rows_per_lane != 16) {
-    msg = "rows_per_lane must be 0, 4, 6, 8, 12 or 16";
+      d.rows_per_lane != 12 && d.rows_per_lane != 16 && d.rows_per_lane != 32) {
+    msg = "rows_per_lane must be 0, 4, 6, 8, 12, 16 or 32";
     return CB_ERR_UNSUPPORTED;
   }
   if (d.lines_per_wg < 0 || d.lines_per_wg > 1024 || (d.lines_per_wg & (d.lines_per_wg - 1)) ||
@@ -807,7 +812,10 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       // strided lines: lane interiors by elimination unless asked otherwise
       // (fewer live registers per lane; PCR if a pivot vanishes)
       SegPlan alt;
-      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max,
+      // FP64 strided lines on uniform lanes take 32 rows per lane when the
+      // lane count allows (32 adjacent lines per workgroup, 256-byte segments)
+      const int m_max_s = d.precision == CB_FP64 ? 32 : m_max;
+      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max_s,
                         d.interior ? d.interior : 3, lcap);
       if (s != CB_OK && d.interior == 0)
         s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, 1, lcap);

@@ -172,7 +172,7 @@ def test_strided_layout_reproduces_oracle(name, n):
     for seg in ((0, 1) if two else (0,)):
         assert np.abs(plan_emulator.solve(p, b, seg) - ref).max() <= 1e-12 * np.abs(ref).max()
     if n == 512:
-        assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (8, 16)
+        assert (info["rows_per_lane"], info["rows_per_lane_strided"]) == (8, 32)
         # automatic interior solve: PCR for unit stride, elimination for strided
         assert (info["interior_elimination"], info["interior_elimination_strided"]) == (0, 1)
     assert p.array(11, 1 if two else 0)[6] == info["interior_elimination_strided"]
