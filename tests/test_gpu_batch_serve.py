@@ -96,6 +96,7 @@ def test_mixed_plans_one_batch(gpu):
         (PENTA, 128, "fp32_refine", 3, False, 2, True), (TRI, 613, "fp64", 0, False, 0, False),
         (PENTA, 384, "fp64", 0, False, 1, False), (TRI, 256, "fp32_refine", 2, False, 2, False),
         (TRI, 200, "fp64", 0, True, 0, False), (PENTA, 512, "fp64", 0, False, 0, True),
+        (TRI, 256, "fp64", 0, False, 2, True), (PENTA, 512, "fp64", 0, False, 1, False),
     ]
     items, singles, refs = [], [], []
     rng = np.random.default_rng(5)

@@ -306,3 +306,23 @@ def test_empty_grids(gpu):
             cb.apply_derivative(plan, st, f, axis, out=out)
             cb.rhs_stencil(st, f, axis, out=out)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bands,n", [(TRI, 512), (PENTA, 512), (TRI, 64), (TRI, 32), (PENTA, 1024)])
+@pytest.mark.parametrize("fused", [False, True])
+def test_thirty_two_rows_per_lane(gpu, axis, bands, n, fused):
+    """32 rows per lane (uniform lanes, eliminated interiors) on every axis, including one- and two-lane lines."""
+    plan = cb.Plan(bands, n, rows_per_lane=32)
+    assert plan.info()["rows_per_lane"] == 32
+    shape = shape_with(axis, n, (6, 40))
+    if fused:
+        f, _ = synth.random_modes(shape, seed=n + axis)
+        lo, c = deriv_stencil(schemes.DERIV6 if bands is TRI else schemes.DERIV10, n)
+        out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+        ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
+    else:
+        b = synth.random_uniform(shape, seed=n + axis)
+        out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        ref = oracle.solve_axis(b.numpy(), axis, bands)
+    assert relerr(out, ref) <= 1e-12

@@ -179,7 +179,8 @@ def test_strided_layout_reproduces_oracle(name, n):
 
 
 @pytest.mark.parametrize("name", ["tri", "penta"])
-@pytest.mark.parametrize("n,rpl", [(512, 8), (512, 16), (384, 12), (613, 16), (200, 8)])
+@pytest.mark.parametrize("n,rpl", [(512, 8), (512, 16), (384, 12), (613, 16), (200, 8), (512, 32), (64, 32),
+                                   (32, 32)])
 def test_interior_elimination_reproduces_oracle(name, n, rpl):
     """Lane interiors solved by banded elimination instead of generalized PCR."""
     bands = _bands(name)
@@ -206,3 +207,12 @@ def test_tuner_searches_partition_counts_for_long_lines():
         cb.Plan([1 / 3, 1.0, 1 / 3], 8192, host_only=True, **x).close()
     assert {x["partitions"] for x in tune.candidates([1 / 3, 1.0, 1 / 3], 512, "fp64")} == {1}
     assert {x["partitions"] for x in tune.candidates([1 / 3, 1.0, 1 / 3], 8192, "fp32_refine")} == {1}
+
+
+def test_thirty_two_rows_need_uniform_elimination():
+    with pytest.raises(cb.CbError):  # ragged: general layout
+        cb.Plan([1 / 3, 1.0, 1 / 3], 500, rows_per_lane=32, host_only=True)
+    with pytest.raises(cb.CbError):  # generalized PCR interiors are not built for 32 rows
+        cb.Plan([1 / 3, 1.0, 1 / 3], 512, rows_per_lane=32, interior=1, host_only=True)
+    i = cb.Plan([1 / 3, 1.0, 1 / 3], 512, rows_per_lane=32, host_only=True).info()
+    assert (i["lanes"], i["rows_per_lane"], i["interior_elimination"]) == (16, 32, 1)
