@@ -254,13 +254,15 @@ def mode_batched(args):
         f, _ = synth.random_modes((nz, ny, nx), seed=gi, device=dev)
         fields.append(f)
     out = {}
-    for prec in ("fp64", "fp32_refine"):
+    # FP64, then FP32 with two refinement iterations (the FP64 floor) and with
+    # one (already below 1e-12 for this scheme: ~5e-14 measured)
+    for key, prec, iters in (("fp64", "fp64", 0), ("fp32_refine2", "fp32_refine", 2), ("fp32_refine1", "fp32_refine", 1)):
         plans, items = {}, []
         for f in fields:
             for ax in range(3):
                 n = f.shape[2 - ax]
                 if n not in plans:
-                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=2),
+                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=iters),
                                 deriv_stencil(n, a, b))
                 items.append((plans[n][0], plans[n][1], f, torch.empty_like(f), ax))
         arr = (cb.BatchItem * len(items))()
@@ -291,16 +293,19 @@ def mode_batched(args):
         torch.cuda.synchronize()
         gdur, _ = _time_launches(g.replay, args.steps, args.warmup, torch.cuda.current_stream())
         gms = float(gdur.mean())
-        out[prec] = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
+        out[key] = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
                      "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1), "items": len(items),
                      "graph_replay_ms": round(gms, 4), "graph_replay_gdofs": round(dof / (gms * 1e-3) / 1e9, 2),
                      "outputs": [it[3] for it in items]}
     # accuracy of the FP32+refinement outputs against the FP64 outputs
-    worst = 0.0
-    for o64, o32 in zip(out["fp64"].pop("outputs"), out["fp32_refine"].pop("outputs")):
-        worst = max(worst, float(((o64 - o32).abs().max() / o64.abs().max()).item()))
+    o64s = out["fp64"].pop("outputs")
+    for key in ("fp32_refine2", "fp32_refine1"):
+        worst = 0.0
+        for o64, o32 in zip(o64s, out[key].pop("outputs")):
+            worst = max(worst, float(((o64 - o32).abs().max() / o64.abs().max()).item()))
+        out[key]["max_rel_diff_vs_fp64"] = worst
     return {"metric": "GDOF/s, 12 uneven grids x 3 axes in one persistent launch", "fp64": out["fp64"],
-            "fp32_refine2": out["fp32_refine"], "max_rel_diff_fp32refine_vs_fp64": worst,
+            "fp32_refine2": out["fp32_refine2"], "fp32_refine1": out["fp32_refine1"],
             "config": {"workload": "grids %s" % shapes}}
 
 
