@@ -362,7 +362,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape per direction first")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this benchmark runs on one GPU only (the multi-GPU split is a design, not part of this build)",
+        print("this benchmark runs on one GPU only (the split across GPUs is designed, not implemented)",
               file=sys.stderr)
         sys.exit(2)
     fn = {"headline": headline, "two_level": mode_two_level, "penta_z": mode_penta_z, "batched": mode_batched,

@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
   CB_OK = 0,
   CB_ERR_INVALID_ARG = 1, /* bad pointer, size, axis, stride or descriptor */
-  CB_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+  CB_ERR_UNSUPPORTED = 2, /* valid request the library does not implement */
   CB_ERR_SINGULAR = 3,    /* cb_plan: a pivot or reduction system is singular */
   CB_ERR_OOM = 4,         /* device allocation failed */
   CB_ERR_HIP = 5          /* a HIP runtime call failed; see cb_last_error() */

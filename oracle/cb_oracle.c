@@ -196,6 +196,8 @@ static int op_apply(const line_op *op, const double *b, double *x, double *tmp) 
 }
 
 /* ---- public: one or many lines of a contiguous (lines x n) array ------- */
+/* x = A^{-1} b per line: the system the compact scheme's left-hand side
+ * defines (Sec. 1 Eq. (1)-(2); cyclic corners as in Sec. 3). */
 int orc_solve_lines(int r, int n, const double *bands, int per_row, int cyclic,
                     int64_t nlines, const double *b, double *x) {
   line_op op;
@@ -227,6 +229,8 @@ static void axis_geometry(const int64_t dims[3], int axis, int64_t *n,
   *nl = dims[u] * dims[v];
 }
 
+/* b = B f along an axis: the right-hand side of Eq. (1) / Eq. (2) (App. A.2
+ * for the staggered stencils), periodic. */
 int orc_stencil_axis(const int64_t dims[3], int axis, int lo, int hi,
                      const double *coef, const double *f, double *out) {
   int64_t n, s, nl, du, su, sv;
@@ -247,6 +251,8 @@ int orc_stencil_axis(const int64_t dims[3], int axis, int lo, int hi,
   return ORC_OK;
 }
 
+/* x = A^{-1} b for every line along an axis (Sec. 5: lines along each index
+ * of a 3D array). */
 int orc_solve_axis(const int64_t dims[3], int axis, int r, const double *bands,
                    int per_row, int cyclic, const double *b, double *x) {
   int64_t n, s, nl, du, su, sv;
@@ -283,7 +289,8 @@ int orc_apply_axis(const int64_t dims[3], int axis, int r, const double *bands,
   return orc_solve_axis(dims, axis, r, bands, 0, cyclic, out, out);
 }
 
-/* Banded matvec y = A x along an axis (used by tests for residuals). */
+/* Banded matvec y = A x along an axis, A the left-hand side of Eq. (1) /
+ * Eq. (2) (used by tests for residuals). */
 int orc_matvec_axis(const int64_t dims[3], int axis, int r, const double *bands,
                     int per_row, int cyclic, const double *x, double *y) {
   int64_t n, s, nl, du, su, sv;
