@@ -48,14 +48,26 @@ def test_c1_32cubed_derivative(gpu, axis):
     assert relerr(out, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("scheme", ["deriv6", "interp6", "deriv10"])
+STAG = [float(schemes.STAG6["alpha"]), 1.0, float(schemes.STAG6["alpha"])]
+
+
+@pytest.mark.parametrize("scheme", ["deriv6", "interp6", "deriv10", "interp6_s2c", "stag6_c2s", "stag6_s2c"])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("n", [64, 96, 192, 256])
 def test_fused_operators(gpu, scheme, axis, n):
+    """Collocated derivatives, collocated<->staggered interpolation and the
+    staggered derivative (Eq. (1), (2), App. A.2), fused with their stencils."""
     shape = shape_with(axis, n)
     f, _ = synth.random_modes(shape, seed=n + axis)
+    h = 2 * math.pi / n
     if scheme == "interp6":
         bands, (lo, c) = INTERP, schemes.stencil_interp_c2s(schemes.INTERP6)
+    elif scheme == "interp6_s2c":
+        bands, (lo, c) = INTERP, schemes.stencil_interp_s2c(schemes.INTERP6)
+    elif scheme == "stag6_c2s":
+        bands, (lo, c) = STAG, schemes.stencil_deriv_c2s(schemes.STAG6, h)
+    elif scheme == "stag6_s2c":
+        bands, (lo, c) = STAG, schemes.stencil_deriv_s2c(schemes.STAG6, h)
     elif scheme == "deriv6":
         bands, (lo, c) = TRI, deriv_stencil(schemes.DERIV6, n)
     else:
