@@ -107,14 +107,19 @@ def test_solve_acyclic_and_per_row(gpu, axis):
         assert relerr(x, ref) <= 1e-12, cyclic
 
 
-def test_solve_in_place_and_strided_view(gpu):
+@pytest.mark.parametrize("P", [1, 4])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+def test_solve_in_place_and_strided_view(gpu, P, bands):
+    """In place on a non-contiguous view (x stride 2), one-partition and
+    partitioned lines; rows outside the view stay untouched."""
     n = 128
+    bd = TRI if bands == "tri" else PENTA
     big = synth.random_uniform((10, 128, 2 * n), seed=5).to(gpu)
     view = big[:, 3:99, ::2]  # non-contiguous: x stride 2
     b = view.cpu().numpy()
-    plan = cb.Plan(TRI, n)
+    plan = cb.Plan(bd, n, partitions=P)
     cb.solve(plan, view, 0, out=view)  # in place on a strided view
-    ref = oracle.solve_axis(np.ascontiguousarray(b), 0, TRI)
+    ref = oracle.solve_axis(np.ascontiguousarray(b), 0, bd)
     assert relerr(view.cpu().numpy(), ref) <= 1e-12
     # rows outside the view are untouched
     before = synth.random_uniform((10, 128, 2 * n), seed=5).numpy()
@@ -351,3 +356,18 @@ def test_single_refinement_meets_tolerance(gpu, axis, bands, n):
     out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
     ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
     assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_longest_one_partition_lines(gpu, axis):
+    """n = 16384 in one workgroup per line (1024 lanes of 16 rows along x, 512
+    lanes of 32 rows strided), on a few lines the oracle solves directly."""
+    n = 16384
+    plan = cb.Plan(TRI, n)
+    i = plan.info()
+    assert (i["lanes"], i["rows_per_lane"]) == (1024, 16)
+    shape = shape_with(axis, n, (3, 2))
+    b = synth.random_uniform(shape, seed=axis)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, TRI)
+    assert relerr(x, ref) <= 1e-12
