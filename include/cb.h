@@ -200,6 +200,9 @@ typedef struct {
   int32_t lanes_strided;         /* equal to the above when one layout serves both */
   int32_t interior_elimination;  /* 1 when lane interiors use banded elimination */
   int32_t interior_elimination_strided; /* the same for strided launches */
+  int32_t partitions_strided;    /* workgroup partitions of strided launches
+                                    (FP64 one-partition plans with n > 4096
+                                    split strided lines into ~1024-row parts) */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 

@@ -57,7 +57,8 @@ class PlanInfo(ctypes.Structure):
                                          ("rows_per_lane_strided", ctypes.c_int32),
                                          ("lanes_strided", ctypes.c_int32),
                                          ("interior_elimination", ctypes.c_int32),
-                                         ("interior_elimination_strided", ctypes.c_int32)]
+                                         ("interior_elimination_strided", ctypes.c_int32),
+                                         ("partitions_strided", ctypes.c_int32)]
 
 
 def lib():

@@ -163,6 +163,14 @@ cb_status upload(Plan &p) {
     p.d_src = reinterpret_cast<const int *>(base + o_src);
     p.d_mats = reinterpret_cast<const double *>(base + o_mats);
   }
+  if (p.strided_wg) {
+    cb_status sw = upload(*p.strided_wg);
+    if (sw != CB_OK) {
+      (void)hipFree(p.dev_base);
+      p.dev_base = nullptr;
+      return sw;
+    }
+  }
   return CB_OK;
 }
 
@@ -215,9 +223,14 @@ cb_status check_stencil(const cb_stencil *st) {
   return CB_OK;
 }
 
+cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
+                    hipStream_t stream);
+
 // --------------------------------------------------------- P = 1 launch --
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                       hipStream_t stream) {
+  // long strided lines: workgroup partitions of the same matrix
+  if (g.rs != 1 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream);
   const int si = g.rs == 1 ? 0 : p.seg_s;  // lane layout for this launch's row stride
   const SegPlan &sp = p.segs[si];
   const bool uni = sp.uniform != 0;
@@ -442,6 +455,10 @@ cb_status cb_plan(const cb_plan_desc *desc, cb_plan_t *out) {
 cb_status cb_plan_destroy(cb_plan_t plan) {
   if (!plan) return CB_OK;
   cb_status s = CB_OK;
+  if (plan->p.strided_wg && plan->p.strided_wg->dev_base) {
+    hipError_t e = hipFree(plan->p.strided_wg->dev_base);
+    if (e != hipSuccess) s = hip_fail(e, "cb_plan_destroy: hipFree");
+  }
   if (plan->p.dev_base) {
     hipError_t e = hipFree(plan->p.dev_base);
     if (e != hipSuccess) s = hip_fail(e, "cb_plan_destroy: hipFree");
@@ -736,11 +753,12 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->red_phases = p.prog.nphase;
   info->red_pcr_steps = p.prog.pcr_steps;
   info->red_detach_steps = p.prog.detach_steps;
-  info->device_bytes = p.dev_bytes;
+  info->device_bytes = p.dev_bytes + (p.strided_wg ? p.strided_wg->dev_bytes : 0);
   info->rows_per_lane_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].M;
   info->lanes_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].L;
   info->interior_elimination = p.segs.empty() ? 0 : p.segs[0].ilu;
   info->interior_elimination_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].ilu;
+  info->partitions_strided = p.strided_wg ? p.strided_wg->P : p.P;
   return CB_OK;
 }
 

@@ -828,6 +828,15 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     p.M = p.segs[0].M;
     p.L = p.segs[0].L;
     p.wg_start = {0, n};
+    if (d.precision == CB_FP64 && n > 4096 && !d.rows_per_lane && !d.lines_per_wg) {
+      cb_plan_desc dw = d;
+      dw.partitions = (n + 512) / 1024;
+      dw.x_staging = 0;
+      dw.interior = 0;
+      auto w = std::make_shared<Plan>();
+      std::string m2;
+      if (build_plan(dw, *w, m2) == CB_OK) p.strided_wg = w;  // else strided lines stay whole
+    }
     if (d.lines_per_wg && d.lines_per_wg * p.L > 1024) {
       msg = "lines_per_wg * lanes exceeds 1024 threads";
       return CB_ERR_INVALID_ARG;

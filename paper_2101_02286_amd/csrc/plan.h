@@ -3,6 +3,7 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/cb.h"
@@ -117,6 +118,10 @@ struct Plan {
   const int *d_row_off = nullptr, *d_src = nullptr;
   const double *d_mats = nullptr;
   const double *d_bands = nullptr;     // n*(2r+1) per-row bands
+  // long FP64 lines (n > 4096) of a one-partition plan: strided launches run
+  // the same matrix split into workgroup partitions of about 1024 rows, since
+  // a whole line per workgroup would leave room for only a few adjacent lines
+  std::shared_ptr<Plan> strided_wg;
 };
 
 // Builds the host-side factorisation.  Returns CB_OK or an error with msg.

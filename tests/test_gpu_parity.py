@@ -371,3 +371,21 @@ def test_longest_one_partition_lines(gpu, axis):
     x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
     ref = oracle.solve_axis(b.numpy(), axis, TRI)
     assert relerr(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+def test_long_strided_lines_use_partitions(gpu, axis, bands):
+    """n = 8192 strided lines run as 8 workgroup partitions (solve and fused derivative)."""
+    bd = TRI if bands == "tri" else PENTA
+    n = 8192
+    plan = cb.Plan(bd, n)
+    assert plan.info()["partitions_strided"] == 8
+    shape = shape_with(axis, n, (5, 3))
+    b = synth.random_uniform(shape, seed=axis)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    assert relerr(x, oracle.solve_axis(b.numpy(), axis, bd)) <= 1e-12
+    f, _ = synth.random_modes(shape, seed=axis + 1)
+    lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12

@@ -216,3 +216,14 @@ def test_thirty_two_rows_need_uniform_elimination():
         cb.Plan([1 / 3, 1.0, 1 / 3], 512, rows_per_lane=32, interior=1, host_only=True)
     i = cb.Plan([1 / 3, 1.0, 1 / 3], 512, rows_per_lane=32, host_only=True).info()
     assert (i["lanes"], i["rows_per_lane"], i["interior_elimination"]) == (16, 32, 1)
+
+
+def test_long_lines_split_strided_launches():
+    """FP64 one-partition plans with n > 4096 solve strided lines in ~1024-row
+    workgroup partitions (unit-stride lines stay whole)."""
+    tri = [1 / 3, 1.0, 1 / 3]
+    assert cb.Plan(tri, 4096, host_only=True).info()["partitions_strided"] == 1
+    i = cb.Plan(tri, 8192, host_only=True).info()
+    assert (i["partitions"], i["partitions_strided"]) == (1, 8)
+    assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
+    assert cb.Plan(tri, 8192, rows_per_lane=16, host_only=True).info()["partitions_strided"] == 1
