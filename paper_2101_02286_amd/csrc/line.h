@@ -82,8 +82,8 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   // MODE_X: a lane's rows are one contiguous 8M-byte run, so one vector load
   // instruction touches many cache lines partially; these loads go through
   // the caches (a streaming hint would drop the lines between the partial
-  // accesses).  MODE_S: every row access is a whole 128-byte segment per 16
-  // lines, read once, so the loads are marked streaming.
+  // accesses).  MODE_S: every row access is a whole 128- or 256-byte segment
+  // of W adjacent lines, read once, so the loads are marked streaming.
   // Staged unit-stride path: the line's L lanes read it with consecutive
   // 8-byte words (whole cache lines per instruction) into an LDS tile where
   // one pad word follows every M words, so each lane's M contiguous rows are

@@ -539,8 +539,9 @@ cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
 // ---------------------------------------------------- segment (lane level) --
 // Lane layout preferences.  Unit-stride launches read a lane's rows as one
 // contiguous run, so fewer rows per lane spread each load instruction over
-// fewer cache lines; strided launches read whole 128-byte row segments and
-// prefer more rows per lane (fewer lanes, fewer block-PCR levels in LDS).
+// fewer cache lines; strided launches read whole row segments of adjacent
+// lines and prefer more rows per lane (fewer lanes, so more lines share a
+// workgroup, and fewer block-PCR levels in LDS).
 enum { PREF_X = 0, PREF_S = 1 };
 
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
