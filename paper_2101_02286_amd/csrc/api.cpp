@@ -331,7 +331,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int L = p.L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
-  NT = std::min(std::max(NT, L), 1024);
+  NT = std::min(std::max(NT, L), k->max_threads);
+  if (L > k->max_threads) return fail(CB_ERR_UNSUPPORTED, "partition needs too many lanes");
   // keep the LDS of phases A and C (lane exchange, coefficients, tile) within
   // the device's LDS per workgroup
   const int RSw = 2 * std::max(p.R, Q);

@@ -71,7 +71,22 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   const int64_t seg0 = a.wg_start[part] + R;  // first row of the interior block D_i
   const int64_t row0 = seg0 + start;
   const bool staged = MODE == MODE_X && tb != nullptr;
+  constexpr int QQ = Q > 0 ? Q : 1;
+  double gp[QQ], gn[QQ];  // staged stencil: halo rows beyond D_i's ends
   if (staged) {
+    // the block-end halo rows (first and last lanes) are read from global
+    // memory together with the tile, so their latency overlaps it
+    if (Q > 0) {
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        const int e0 = start - QQ + i, e1 = start + m + i;
+        int64_t r0 = seg0 + e0, r1 = seg0 + e1;
+        r0 = r0 < 0 ? r0 + a.n : r0;
+        r1 = r1 >= a.n ? r1 - a.n : r1;
+        gp[i] = (active && e0 < 0) ? a.in[base + r0 * a.rs] : 0.0;
+        gn[i] = (active && e1 >= S) ? a.in[base + r1 * a.rs] : 0.0;
+      }
+    }
     const double *lin = a.in + base + seg0;
     double t[M];
 #pragma unroll
@@ -93,26 +108,13 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
   }
   if (Q > 0) {  // fused stencil; the halo at the block's ends comes from global memory
-    constexpr int QQ = Q > 0 ? Q : 1;
     double fp[QQ], fn[QQ];
-    if (staged) {  // neighbours inside D_i from the tile, beyond its ends from global memory
+    if (staged) {  // neighbours inside D_i from the tile, beyond its ends prefetched
 #pragma unroll
       for (int i = 0; i < QQ; ++i) {
         const int e0 = start - QQ + i, e1 = start + m + i;
-        if (e0 >= 0) {
-          fp[i] = tb[tile_at<M>(e0)];
-        } else {
-          int64_t r = seg0 + e0;
-          r = r < 0 ? r + a.n : r;
-          fp[i] = active ? a.in[base + r * a.rs] : 0.0;
-        }
-        if (e1 < S) {
-          fn[i] = tb[tile_at<M>(e1)];
-        } else {
-          int64_t r = seg0 + e1;
-          r = r >= a.n ? r - a.n : r;
-          fn[i] = active ? a.in[base + r * a.rs] : 0.0;
-        }
+        fp[i] = e0 >= 0 ? tb[tile_at<M>(e0)] : gp[i];
+        fn[i] = e1 < S ? tb[tile_at<M>(e1)] : gn[i];
       }
     } else {
       halo<QQ, M>(v, m, false, p, xc, fp, fn);
@@ -169,8 +171,15 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     solve_segment<R, M, double, false, CSRC_GLOBAL>(v, sg, p, type, m, xc);
 }
 
+// Workgroup bound of the partitioned kernels: unit-stride 16-row instances
+// (LDS tile plus general-layout coefficients) get 256 VGPRs at 512 threads.
+template <int M, int MODE>
+constexpr int wg_max_threads() {
+  return (MODE == MODE_X && M > 8) ? 512 : 1024;
+}
+
 template <int R, int M, int MODE, int Q>
-__global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
+__global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgArgs a) {
   extern __shared__ double smem[];
   LanePos p;
   int64_t line, base;
@@ -178,6 +187,18 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   wg_setup<R, M, MODE>(a, p, line, active, base);
   Xchg xc{smem, (Q > R ? 2 * Q : 2 * R), (int)blockDim.x, 0, true};
   const int part = blockIdx.y;
+  // inputs of the partition's interface rows g0..g0+R-1 (with the +-3
+  // stencil neighbours), read before the interior solve so their latency
+  // overlaps it
+  constexpr int QI = Q > 0 ? 3 : 0;
+  double iv[R + 2 * QI];
+  const int64_t g0 = a.wg_start[part];
+#pragma unroll
+  for (int j = 0; j < R + 2 * QI; ++j) {
+    int64_t r = g0 - QI + j;
+    r = r < 0 ? r + a.n : (r >= a.n ? r - a.n : r);
+    iv[j] = (active && p.l == 0) ? a.in[base + r * a.rs] : 0.0;
+  }
   double v[M];
   int start, m;
   const double none[R] = {};
@@ -187,19 +208,15 @@ __global__ __launch_bounds__(1024) void k_wg_a(const WgArgs a) {
   if (!active) return;
   double *sc = a.scratch + (line * a.P + part) * 3 * R;
   if (p.l == 0) {
-    const int64_t g0 = a.wg_start[part];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       double bt;
-      if (Q > 0) {  // stencil at the partition's interface row g0 + c
+      if constexpr (Q > 0) {  // stencil at the partition's interface row g0 + c
         bt = 0.0;
-        for (int q = -3; q <= 3; ++q) {
-          int64_t r = g0 + c + q;
-          r = r < 0 ? r + a.n : (r >= a.n ? r - a.n : r);
-          bt += a.stc[q + 3] * a.in[base + r * a.rs];
-        }
+#pragma unroll
+        for (int q = -3; q <= 3; ++q) bt += a.stc[q + 3] * iv[c + q + QI];
       } else {
-        bt = a.in[base + (g0 + c) * a.rs];
+        bt = iv[c];
       }
       sc[c] = bt;         // b~_i
       sc[R + c] = v[c];   // first R rows of y_i
@@ -290,7 +307,7 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
 // Phase C: x_i = D_i^{-1}[b_i - L_i x~_i - U_i x~_{i+1}] (Eq. (9), equal to
 // the back-substitution of Eq. (22)) from the interface values of phase B.
 template <int R, int M, int MODE, int Q>
-__global__ __launch_bounds__(1024) void k_wg_c(const WgArgs a) {
+__global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgArgs a) {
   extern __shared__ double smem[];
   constexpr int RS = Q > R ? 2 * Q : 2 * R;
   LanePos p;
@@ -398,8 +415,8 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
 }
 
 #define CB_WG_INST(R, M, MODE, Q)                                                                      \
-  {R, M, MODE, Q, (const void *)&k_wg_a<R, M, MODE, Q>, (const void *)&k_wg_b<R>,                       \
-   (const void *)&k_wg_c<R, M, MODE, Q>}
+  {R, M, MODE, Q, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, M, MODE, Q>,                       \
+   (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q>}
 #define CB_WG_Q(R, M, MODE) CB_WG_INST(R, M, MODE, 0), CB_WG_INST(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {
     CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),

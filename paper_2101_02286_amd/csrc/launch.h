@@ -80,6 +80,7 @@ struct LineKernel {
 };
 struct WgKernel {
   int R, M, mode, Q;
+  int max_threads;                 // workgroup size bound of phases A and C
   const void *fn_a, *fn_b, *fn_c;  // phases A (interiors), B (reduced system), C (back-substitution)
 };
 
