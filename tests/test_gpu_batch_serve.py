@@ -198,3 +198,37 @@ def test_server_results_same_alone_and_in_mix(gpu):
         bands = TRI if r.scheme == "tri6" else PENTA
         ref = oracle.apply_axis(f, r.axis, bands, stc.lo, stc.coefs)
         assert relerr(out_mix, ref) <= 1e-12, r.rid
+
+
+@pytest.mark.parametrize("precision,iters", [("fp64", 0), ("fp32_refine", 2), ("fp32_refine", 1)])
+def test_uneven_grid_batch_full_size_sampled(gpu, precision, iters):
+    """The benchmark's batch (12 uneven grids x 3 axes, seeded shapes and
+    inputs, one launch per kernel class) at full size, checked on sampled
+    lines of every item against the oracle."""
+    shapes = synth.grid_batch_shapes(seed=0, count=12)
+    items, fields, plans = [], [], {}
+    for gi, (nx, ny, nz) in enumerate(shapes):
+        f, _ = synth.random_modes((nz, ny, nx), seed=gi, device=gpu)
+        fields.append(f)
+        for axis in range(3):
+            n = (nx, ny, nz)[axis]
+            if n not in plans:
+                lo, c = stencil_for("tri6", n)
+                plans[n] = (cb.Plan(TRI, n, precision=precision, refine_iters=iters), cb.Stencil(lo, c), lo, c)
+            items.append((plans[n][0], plans[n][1], f, torch.empty_like(f), axis))
+    launch(batch(items))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for plan, st, f, out, axis in items:
+        n = f.shape[2 - axis]
+        lo, c = plans[n][2], plans[n][3]
+        nz, ny, nx = f.shape
+        du, dv = [(ny, nz), (nx, nz), (nx, ny)][axis]
+        picks = [(int(rng.integers(du)), int(rng.integers(dv))) for _ in range(6)] + [(du - 1, dv - 1)]
+        fl, ol = [], []
+        for u, v in picks:
+            sel = (v, u, slice(None)) if axis == 0 else ((v, slice(None), u) if axis == 1 else (slice(None), v, u))
+            fl.append(f[sel].cpu().numpy())
+            ol.append(out[sel].cpu().numpy())
+        ref = oracle.apply_axis(np.stack(fl)[None], 0, TRI, lo, c)[0]
+        assert relerr(np.stack(ol), ref) <= 1e-12, (f.shape, axis)
