@@ -149,6 +149,17 @@ def test_matvec_vs_dense():
     assert np.abs(y - f @ A.T).max() <= 1e-14
 
 
+def test_matvec_acyclic_per_row_vs_dense():
+    """Acyclic per-row matvec along y against a dense product."""
+    n = 13
+    bands = synth.random_bands(n, 2, seed=9)
+    f = np.random.default_rng(10).standard_normal((3, n, 4))
+    y = oracle.matvec_axis(f, 1, bands, cyclic=False, per_row=True)
+    A = dense_matrix(bands, n, False, per_row=True)
+    ref = np.einsum("jk,zkx->zjx", A, f)
+    assert np.abs(y - ref).max() <= 1e-14
+
+
 # ----------------------------------------------------- closed forms (Eq. 1, 2)
 def modified_wavenumber(s, kh):
     a, b, c = float(s["a"]), float(s["b"]), float(s.get("c", 0))
@@ -300,6 +311,15 @@ MUTATIONS = [
      "for (int j = j0 + 1; j < i; ++j) s -= lu[i * w + (j - i + r)] * x[j];"),
     # corner rows mis-indexed (off by one)
     ("op->crow[r + k] = n - r + k;", "op->crow[r + k] = n - r + k - 1;"),
+    # Woodbury capacitance built as -I + V^T Z (a sign)
+    ("double s = (i == k) ? 1.0 : 0.0;", "double s = (i == k) ? -1.0 : 0.0;"),
+    # stencil coefficients applied in reverse order (a transposed operand)
+    ("acc += coef[q - lo] * f[base + jj * s];", "acc += coef[hi - q] * f[base + jj * s];"),
+    # acyclic matvec wraps around the ends (a dropped boundary condition)
+    ("if (!cyclic && (c < 0 || c >= n)) continue;", "(void)cyclic;"),
+    # the corner correction applied with the wrong sign
+    ("for (int i = 0; i < n; ++i) x[i] -= op->z[k * n + i] * t[k];",
+     "for (int i = 0; i < n; ++i) x[i] += op->z[k * n + i] * t[k];"),
 ]
 
 
@@ -332,6 +352,9 @@ def test_pins_catch_planted_mistakes(mi, tmp_path, monkeypatch):
         lambda: test_solve_vs_fft_circulant("deriv10", 256),
         lambda: test_stencil_vs_dense_circulant(-2, [0.1, -0.7, 0.0, 0.7, -0.1]),
         lambda: test_derivative_closed_form("deriv6"),
+        lambda: test_matvec_vs_dense(),
+        lambda: test_matvec_acyclic_per_row_vs_dense(),
+        lambda: test_axes_consistent_with_lines(),
     ]
     failed = 0
     for chk in checks:
