@@ -304,6 +304,10 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   a.refine_iters = p.refine_iters;
   a.coef_lds = coef_lds ? 1 : 0;
   a.stage_x = stage_x ? 1 : 0;
+  a.stage_vec = (stage_x && g.n % 2 == 0 && sp.M % 2 == 0 && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0 &&
+                 (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0))
+                    ? 1
+                    : 0;
   a.n = (int)g.n;
   a.stage_off = (int64_t)NT * 2 * RS + (int64_t)coef_dbl;
   a.stage_pitch = pitch;
@@ -651,6 +655,11 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.refine_iters = p.refine_iters;
     a.coef_lds = coef_lds ? 1 : 0;
     a.stage_x = stage ? 1 : 0;
+    a.stage_vec = (stage && g.n % 2 == 0 && sp.M % 2 == 0 && (uintptr_t)it.in % 16 == 0 &&
+                   (uintptr_t)it.out % 16 == 0 && (g.nu == 1 || g.su % 2 == 0) &&
+                   (g.nlines <= g.nu || g.sv % 2 == 0))
+                      ? 1
+                      : 0;
     a.stage_off = (int64_t)W * L * 2 * RS + (coef_lds ? (int64_t)coef_dbl_if : 0);
     a.stage_pitch = pitch;
     a.seg = p.segdev_host[si];

@@ -33,6 +33,7 @@ struct LineArgs {
   int lgL, lgW, block_sync, refine_iters;
   int coef_lds;              // general layout: coefficient blocks staged in LDS
   int stage_x;               // unit-stride lines go through an LDS tile
+  int stage_vec;             // ... read and written as 16-byte pairs (even n, aligned lines)
   int n;                     // line length
   int64_t stage_off;         // LDS offset (doubles) of the tile
   int64_t stage_pitch;       // doubles per line in the tile (n + n/M + 1)

@@ -93,16 +93,34 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   double b64[M];
   if (staged) {
     const double *lin = a.in + base;
-    double t[M];
+    if (a.stage_vec) {  // 16-byte pairs: rows 2e, 2e+1 share a pad group (M even)
+      const dbl2 *lin2 = reinterpret_cast<const dbl2 *>(lin);
+      dbl2 t2[M / 2];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int e = p.l + k * p.L;
-      t[k] = (active && e < nrow) ? __builtin_nontemporal_load(lin + e) : 0.0;
-    }
+      for (int k = 0; k < M / 2; ++k) {
+        const int e2 = p.l + k * p.L;
+        t2[k] = (active && 2 * e2 < nrow) ? __builtin_nontemporal_load(lin2 + e2) : dbl2{0.0, 0.0};
+      }
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int e = p.l + k * p.L;
-      if (e < nrow) tb[e + e / M] = t[k];
+      for (int k = 0; k < M / 2; ++k) {
+        const int e = 2 * (p.l + k * p.L);
+        if (e < nrow) {
+          tb[e + e / M] = t2[k].x;
+          tb[e + e / M + 1] = t2[k].y;
+        }
+      }
+    } else {
+      double t[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int e = p.l + k * p.L;
+        t[k] = (active && e < nrow) ? __builtin_nontemporal_load(lin + e) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int e = p.l + k * p.L;
+        if (e < nrow) tb[e + e / M] = t[k];
+      }
     }
     xc.sync();
 #pragma unroll
@@ -214,10 +232,19 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     xc.sync();
     if (!active) return;
     double *lout = a.out + base;
+    if (a.stage_vec) {
+      dbl2 *lout2 = reinterpret_cast<dbl2 *>(lout);
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int e = p.l + k * p.L;
-      if (e < nrow) __builtin_nontemporal_store(tb[e + e / M], lout + e);
+      for (int k = 0; k < M / 2; ++k) {
+        const int e = 2 * (p.l + k * p.L);
+        if (e < nrow) __builtin_nontemporal_store(dbl2{tb[e + e / M], tb[e + e / M + 1]}, lout2 + e / 2);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int e = p.l + k * p.L;
+        if (e < nrow) __builtin_nontemporal_store(tb[e + e / M], lout + e);
+      }
     }
     return;
   }
