@@ -261,10 +261,19 @@ def mode_batched(args):
         for f in fields:
             for ax in range(3):
                 n = f.shape[2 - ax]
-                if n not in plans:
-                    plans[n] = (cb.Plan(bands, n, precision=prec, refine_iters=iters),
-                                deriv_stencil(n, a, b))
-                items.append((plans[n][0], plans[n][1], f, torch.empty_like(f), ax))
+                # --tune: the autotuner's choice (rows per lane, interior solve,
+                # ...) per grid shape and axis; else one default plan per n
+                key_p = (n, tuple(f.shape), ax) if args.tune else n
+                if key_p not in plans:
+                    st = deriv_stencil(n, a, b)
+                    if args.tune:
+                        from paper_2101_02286_amd import tune
+                        best, _ = tune.tune(bands, n, f, ax, stencil=st, precision=prec, refine_iters=iters,
+                                            reps=3, cache=None, one_partition=True)
+                        plans[key_p] = (cb.Plan(bands, n, precision=prec, refine_iters=iters, **best), st)
+                    else:
+                        plans[key_p] = (cb.Plan(bands, n, precision=prec, refine_iters=iters), st)
+                items.append((plans[key_p][0], plans[key_p][1], f, torch.empty_like(f), ax))
         arr = (cb.BatchItem * len(items))()
         for i, (pl, st, f, o, ax) in enumerate(items):
             arr[i].plan = pl.h
@@ -306,7 +315,7 @@ def mode_batched(args):
         out[key]["max_rel_diff_vs_fp64"] = worst
     return {"metric": "GDOF/s, 12 uneven grids x 3 axes in one persistent launch", "fp64": out["fp64"],
             "fp32_refine2": out["fp32_refine2"], "fp32_refine1": out["fp32_refine1"],
-            "config": {"workload": "grids %s" % shapes}}
+            "config": {"workload": "grids %s" % shapes, "autotuned": bool(args.tune)}}
 
 
 def mode_serve(args):

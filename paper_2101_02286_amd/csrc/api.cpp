@@ -259,9 +259,10 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (p.desc.lines_per_wg > 0) {
     W = p.desc.lines_per_wg;
   } else if (mode == MODE_X) {
-    // staged unit-stride lines: one line per workgroup measured best (512^3);
-    // direct loads: 512-thread workgroups
-    W = stage_x ? 1 : std::max(1, 512 / L);
+    // staged unit-stride lines: one line per workgroup measured best (512^3),
+    // but at least one wavefront per workgroup for short lines; direct loads:
+    // 512-thread workgroups
+    W = stage_x ? std::max(1, 64 / L) : std::max(1, 512 / L);
   } else {
     // adjacent lines: 16 (128-byte row segments), 32 with 32 rows per lane
     W = std::max(1, std::min(sp.M == 32 ? 32 : 16, 1024 / L));

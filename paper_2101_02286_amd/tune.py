@@ -81,9 +81,10 @@ def _time(fn, reps, stream):
 
 
 def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps=5, cache=DEFAULT_CACHE,
-         max_candidates=None):
-    """Return (best_kwargs, table) for solving/deriving along `axis` of tensor f."""
-    key = _key(bands, n, precision, tuple(f.shape), axis, stencil is not None)
+         max_candidates=None, one_partition=False):
+    """Return (best_kwargs, table) for solving/deriving along `axis` of tensor f
+    (`one_partition`: only P = 1 plans, e.g. for batched launches)."""
+    key = _key(bands, n, precision, tuple(f.shape), axis, stencil is not None) + ("|p1" if one_partition else "")
     db = {}
     if cache and os.path.exists(cache):
         try:
@@ -96,6 +97,8 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
     out = torch.empty_like(f)
     table = []
     cands = candidates(bands, n, precision)
+    if one_partition:
+        cands = [c for c in cands if c["partitions"] == 1]
     if max_candidates:
         cands = cands[:max_candidates]
     for c in cands:
