@@ -76,7 +76,8 @@ typedef struct {
                             power of two).  0 = let the library choose (1). */
   int32_t precision;     /* cb_precision */
   int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations (0 -> 2) */
-  int32_t rows_per_lane; /* 0 = automatic; else 4, 6, 8, 12 or 16 */
+  int32_t rows_per_lane; /* 0 = automatic; else 4, 6, 8, 12, 16 or 32 (32:
+                            uniform lanes with interior elimination only) */
   int32_t host_only;     /* 1: factorise on the host only (no device memory is
                             touched); such a plan can be inspected with
                             cb_plan_get_* but solve calls reject it */
@@ -95,7 +96,14 @@ typedef struct {
                              (unit-stride launches: 1 on uniform lanes, 2 on
                              general ones; strided launches: 2 where
                              available), 1 generalized PCR (Sec. 2), 2 banded
-                             elimination in registers (rows_per_lane 8/12/16) */
+                             elimination in registers (rows_per_lane 8/12/16/32) */
+  int32_t tile_order;     /* strided launches: order in which workgroups take
+                             the tiles of adjacent lines.  0 automatic (2 when
+                             a tile's row segments are narrower than 128 bytes
+                             or its rows lie at most 64 KB apart, else 1),
+                             1 launch order, 2 grouped by XCD: the
+                             workgroups one XCD runs take consecutive tiles, so
+                             neighbouring segments share that XCD's L2 */
 } cb_plan_desc;
 
 /* A strided 3D array of FP64: element (i0,i1,i2) at ptr[i0*stride[0] +

@@ -33,7 +33,8 @@ class PlanDesc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
                 ("rows_per_lane", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("lines_per_wg", ctypes.c_int32), ("block_barriers", ctypes.c_int32),
-                ("x_staging", ctypes.c_int32), ("interior", ctypes.c_int32)]
+                ("x_staging", ctypes.c_int32), ("interior", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -113,14 +114,15 @@ class Plan:
 
     def __init__(self, bands, n, cyclic=True, partitions=1, precision="fp64", refine_iters=0,
                  rows_per_lane=0, per_row=False, host_only=False, lines_per_wg=0, block_barriers=0,
-                 x_staging=0, interior=0):
+                 x_staging=0, interior=0, tile_order=0):
         import numpy as np
         b = np.ascontiguousarray(np.asarray(bands, dtype=np.float64))
         r = (b.shape[-1] - 1) // 2
         self._bands = b
         d = PlanDesc(r, n, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(per_row), int(cyclic),
                      int(partitions), PRECISIONS[precision], int(refine_iters), int(rows_per_lane),
-                     int(host_only), int(lines_per_wg), int(block_barriers), int(x_staging), int(interior))
+                     int(host_only), int(lines_per_wg), int(block_barriers), int(x_staging), int(interior),
+                     int(tile_order))
         h = ctypes.c_void_p()
         _check(lib().cb_plan(ctypes.byref(d), ctypes.byref(h)))
         self.h = h

@@ -56,6 +56,22 @@ size_t lds_cap() {
   return cap;
 }
 
+// Number of XCDs (chiplets with their own L2) of the current device; 1 when
+// the runtime does not report it.
+int xcd_count() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || v < 1) v = 1;
+  cache[dev] = v;
+  return v;
+}
+
 cb_status fail(cb_status s, const std::string &m) {
   g_err = m;
   return s;
@@ -264,8 +280,13 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
     // 512-thread workgroups
     W = stage_x ? std::max(1, 64 / L) : std::max(1, 512 / L);
   } else {
-    // adjacent lines: 16 (128-byte row segments), 32 with 32 rows per lane
+    // adjacent lines: 16 (128-byte row segments), 32 with 32 rows per lane.
+    // FP32 lines with refinement: at most 512 threads unless that leaves
+    // fewer than 8 lines (their three solves pass more workgroup barriers,
+    // which cost more in larger workgroups: measured 189 vs 154 GDOF/s for
+    // 8 vs 16 lines of 64 lanes)
     W = std::max(1, std::min(sp.M == 32 ? 32 : 16, 1024 / L));
+    if (fp32 && p.refine_iters > 0) W = std::min(W, std::max(8, 512 / L));
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread (2r when the
   // unit-stride tile is staged: its halo comes from the tile), within the
@@ -319,6 +340,15 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const size_t lds = lds_of(W);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
+  // Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
+  // turn, so in launch order neighbouring tiles run on different XCDs):
+  // automatic when row segments are narrower than a 128-byte L2 line (its
+  // tiles then share lines) or rows lie at most 64 KB apart (measured: 3-4 KB
+  // row strides gain 4-10 %, 1.5-2 MB ones lose 4-10 % with wide segments)
+  const bool xcd_order =
+      mode == MODE_S && (p.desc.tile_order == 2 ||
+                         (p.desc.tile_order == 0 && (W * 8 < 128 || g.rs * (int64_t)sizeof(double) <= 65536)));
+  a.xcds = xcd_order ? xcd_count() : 1;
   void *args[] = {&a};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(NT), args, lds, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -626,7 +656,9 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     }
     if (mode == MODE_S) {
       bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_S);
-      if (bk) nt = std::min(bk->threads, std::max(512, 16 * L));
+      // 512 threads, or 16 lines (8 with FP32 refinement, as in launch_line)
+      // where lanes need more
+      if (bk) nt = std::min(bk->threads, std::max(512, (fp && p.refine_iters > 0 ? 8 : 16) * L));
       if (bk && L <= nt) W = nt / L;
     }
     if (!bk || W == 0)

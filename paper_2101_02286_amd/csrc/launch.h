@@ -35,6 +35,7 @@ struct LineArgs {
   int stage_x;               // unit-stride lines go through an LDS tile
   int stage_vec;             // ... read and written as 16-byte pairs (even n, aligned lines)
   int n;                     // line length
+  int xcds;                  // > 1: tiles in XCD-grouped order over this many XCDs
   int64_t stage_off;         // LDS offset (doubles) of the tile
   int64_t stage_pitch;       // doubles per line in the tile (n + n/M + 1)
   SegDev seg;

@@ -15,9 +15,9 @@ namespace cb {
 // tile plus per-lane coefficients); FP32 instances carry the FP64
 // refinement state beside the FP32 reduction and get up to 256 VGPRs by
 // allowing at most 512 threads.
-template <int M, typename T, int MODE, bool UNI>
+template <int R, int M, typename T, int MODE, bool UNI>
 constexpr int line_max_threads() {
-  return sizeof(T) == 4 ? 512 : ((UNI || MODE == 1) ? 1024 : 512);
+  return sizeof(T) == 4 ? ((R == 1 && M <= 8 && MODE == 1) ? 1024 : 512) : ((UNI || MODE == 1) ? 1024 : 512);
 }
 
 // Exchange region size (doubles per thread and region): the halo exchange
@@ -265,9 +265,17 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
 }
 
 template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU>
-__global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_line(const LineArgs a) {
+__global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_line(const LineArgs a) {
   extern __shared__ double smem[];
-  line_tile<R, M, T, MODE, Q, UNI, ILU>(a, (int64_t)blockIdx.x, smem);
+  uint32_t tile = blockIdx.x;
+  if (a.xcds > 1) {
+    // workgroup b runs on XCD b mod X; XCD j takes the j-th contiguous range
+    // of tiles (the first G mod X ranges one tile longer), in order
+    const uint32_t X = (uint32_t)a.xcds, G = gridDim.x, q = G / X, rem = G % X;
+    const uint32_t j = tile % X, s = tile / X;
+    tile = j * q + (j < rem ? j : rem) + s;
+  }
+  line_tile<R, M, T, MODE, Q, UNI, ILU>(a, (int64_t)tile, smem);
 }
 
 
@@ -281,7 +289,7 @@ __global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_line(
 // replayed (e.g. from a captured graph) without a memset.
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, bool UNI, bool ILU, int MODE>
-__global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
+__global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
                                                                                const BatchItemDev *items) {
   extern __shared__ double smem[];
   __shared__ int64_t s_tile;
@@ -314,14 +322,14 @@ __global__ __launch_bounds__((line_max_threads<M, T, MODE, UNI>())) void k_batch
 }
 
 #define CB_BATCH_INST(R, M, T, UNI, ILU, MODE)                                                 \
-  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, MODE, line_max_threads<M, T, MODE, UNI>(),          \
+  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, MODE, line_max_threads<R, M, T, MODE, UNI>(),          \
    (const void *)&k_batched<R, M, T, UNI, ILU, MODE>}
 #define CB_BATCH_MODE(R, M, T, UNI, ILU) CB_BATCH_INST(R, M, T, UNI, ILU, MODE_X), CB_BATCH_INST(R, M, T, UNI, ILU, MODE_S)
 #define CB_BATCH_T(R, M, UNI, ILU) CB_BATCH_MODE(R, M, double, UNI, ILU), CB_BATCH_MODE(R, M, float, UNI, ILU)
 #define CB_BATCH_R(M, UNI, ILU) CB_BATCH_T(1, M, UNI, ILU), CB_BATCH_T(2, M, UNI, ILU)
 
 #define CB_LINE_INST(R, M, T, MODE, Q, UNI, ILU) \
-  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<M, T, MODE, UNI>(), \
+  {R, M, sizeof(T) == 8 ? 0 : 1, MODE, Q, UNI, ILU, line_max_threads<R, M, T, MODE, UNI>(), \
    (const void *)&k_line<R, M, T, MODE, Q, UNI, ILU>}
 #define CB_LINE_Q(R, M, T, MODE, UNI, ILU)                                             \
   CB_LINE_INST(R, M, T, MODE, 0, UNI, ILU), CB_LINE_INST(R, M, T, MODE, 2, UNI, ILU), \

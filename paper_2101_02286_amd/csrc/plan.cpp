@@ -747,8 +747,9 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   }
   if (d.lines_per_wg < 0 || d.lines_per_wg > 1024 || (d.lines_per_wg & (d.lines_per_wg - 1)) ||
       d.block_barriers < 0 || d.block_barriers > 1 || d.x_staging < 0 || d.x_staging > 2 || d.interior < 0 ||
-      d.interior > 2) {
-    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1; x_staging and interior 0..2";
+      d.interior > 2 || d.tile_order < 0 || d.tile_order > 2) {
+    msg = "lines_per_wg must be 0 or a power of two <= 1024; block_barriers 0 or 1; x_staging, interior and "
+          "tile_order 0..2";
     return CB_ERR_INVALID_ARG;
   }
   const int R = d.r, n = d.n, W = 2 * R + 1;

@@ -11,6 +11,7 @@ For one (bands, n, precision, grid shape, axis) it times every valid choice of
   * x_staging     -- unit-stride lines read directly or through an LDS tile,
   * interior      -- lane interiors by generalized PCR or banded elimination
                      (the latter for 8, 12 or 16 rows per lane),
+  * tile_order    -- strided lines: tiles in launch order or grouped by XCD,
 with HIP events on the launch stream, and returns the fastest.  Results are
 cached in a JSON file keyed by the problem so a process tunes once.
 """
@@ -35,8 +36,12 @@ def _key(bands, n, precision, shape, axis, fused):
 PARTS = (2, 4, 8, 16)
 
 
-def candidates(bands, n, precision):
+def candidates(bands, n, precision, strided=None):
+    """Launch choices to time.  `strided` True: rows are strided (x_staging is
+    moot; both tile orders are tried); False: unit-stride rows; None: both."""
     out = []
+    xss = (0,) if strided else (1, 2)
+    orders = (1, 2) if strided else (0,)
     if precision == "fp64" and n >= 1024:
         for P in PARTS:
             for rpl in (8, 16):
@@ -45,9 +50,9 @@ def candidates(bands, n, precision):
                 except cb.CbError:
                     continue
                 for w in (0, 2, 4, 8):
-                    for xs in (1, 2):
+                    for xs in xss:
                         out.append(dict(partitions=P, rows_per_lane=rpl, lines_per_wg=w, block_barriers=0,
-                                        x_staging=xs, interior=1))
+                                        x_staging=xs, interior=1, tile_order=0))
     for rpl in ROWS:
         try:
             p = cb.Plan(bands, n, precision=precision, rows_per_lane=rpl, host_only=True)
@@ -59,10 +64,11 @@ def candidates(bands, n, precision):
             if w and w * L > 1024:
                 continue
             for bb in (0, 1):
-                for xs in (1, 2):
+                for xs in xss:
                     for it in ((1, 2) if rpl in (8, 12, 16) else (1,)):
-                        out.append(dict(partitions=1, rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb,
-                                        x_staging=xs, interior=it))
+                        for to in orders:
+                            out.append(dict(partitions=1, rows_per_lane=rpl, lines_per_wg=w, block_barriers=bb,
+                                            x_staging=xs, interior=it, tile_order=to))
     return out
 
 
@@ -96,7 +102,7 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
     stream = torch.cuda.current_stream()
     out = torch.empty_like(f)
     table = []
-    cands = candidates(bands, n, precision)
+    cands = candidates(bands, n, precision, strided=f.stride(2 - axis) != 1)
     if one_partition:
         cands = [c for c in cands if c["partitions"] == 1]
     if max_candidates:
@@ -119,7 +125,7 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
         p.close()
     best = min(table, key=lambda r: r["ms"])
     best = {k: best[k] for k in ("partitions", "rows_per_lane", "lines_per_wg", "block_barriers", "x_staging",
-                                 "interior")}
+                                 "interior", "tile_order")}
     if cache:
         db[key] = {"best": best, "table": table}
         os.makedirs(os.path.dirname(cache), exist_ok=True)

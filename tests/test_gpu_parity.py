@@ -389,3 +389,22 @@ def test_long_strided_lines_use_partitions(gpu, axis, bands):
     lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
     out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
     assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("n", [96, 512, 613])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_tile_orders(gpu, axis, n, prec):
+    """Strided tiles taken in launch order (1) or XCD-grouped order (2): the
+    same lines are solved, bit for bit, with a tile count that is not a
+    multiple of the XCD count and a partial last tile (407 lines)."""
+    f, _ = synth.random_modes(shape_with(axis, n, (37, 11)), seed=n + axis)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    fd = f.to(gpu)
+    outs = []
+    for order in (1, 2):
+        plan = cb.Plan(TRI, n, precision=prec, tile_order=order)
+        outs.append(cb.apply_derivative(plan, cb.Stencil(lo, c), fd, axis).cpu().numpy())
+    ref = oracle.apply_axis(f.numpy(), axis, TRI, lo, c)
+    assert relerr(outs[1], ref) <= 1e-12
+    assert np.array_equal(outs[0], outs[1])

@@ -132,6 +132,12 @@ def test_bad_descriptors():
         cb.Plan([1 / 3, 1, 1 / 3], 2, host_only=True)
     with pytest.raises(cb.CbError):
         cb.Plan([1 / 3, 1, 1 / 3], 64, rows_per_lane=5, host_only=True)
+    for order in (-1, 3):
+        with pytest.raises(cb.CbError) as e:
+            cb.Plan([1 / 3, 1, 1 / 3], 64, tile_order=order, host_only=True)
+        assert e.value.status == cb.CB_ERR_INVALID_ARG
+    for order in (0, 1, 2):
+        cb.Plan([1 / 3, 1, 1 / 3], 64, tile_order=order, host_only=True)
 
 
 def test_tuner_candidates_are_valid_layouts():
@@ -144,6 +150,13 @@ def test_tuner_candidates_are_valid_layouts():
         assert x["lines_per_wg"] * L <= 1024
     c5 = tune.candidates([1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20], 613, "fp32_refine")
     assert {x["rows_per_lane"] for x in c5} == {8, 16}  # ragged lines use the general layouts
+    # strided rows: both tile orders, no unit-stride staging choice
+    cs = tune.candidates([1 / 3, 1.0, 1 / 3], 512, "fp64", strided=True)
+    assert {x["tile_order"] for x in cs} == {1, 2} and {x["x_staging"] for x in cs} == {0}
+    cx = tune.candidates([1 / 3, 1.0, 1 / 3], 512, "fp64", strided=False)
+    assert {x["tile_order"] for x in cx} == {0} and {x["x_staging"] for x in cx} == {1, 2}
+    for x in cs[:8] + cx[:8]:
+        cb.Plan([1 / 3, 1.0, 1 / 3], 512, host_only=True, **x).close()
 
 
 def test_deep_levels_with_decayed_couplings():
