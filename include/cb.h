@@ -93,8 +93,8 @@ typedef struct {
                              tile fits in 64 KB of LDS, else 1), 1 lanes load
                              their rows directly, 2 through a coalesced LDS tile */
   int32_t interior;       /* solve of each lane's interior block D_l: 0 automatic
-                             (unit-stride launches: 1 on uniform lanes, 2 on
-                             general ones; strided launches: 2 where
+                             (unit-stride launches: 1 on uniform FP64 lanes,
+                             else 2 where available; strided launches: 2 where
                              available), 1 generalized PCR (Sec. 2), 2 banded
                              elimination in registers (rows_per_lane 8/12/16/32) */
   int32_t tile_order;     /* strided launches: order in which workgroups take

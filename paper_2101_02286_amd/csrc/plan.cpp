@@ -801,10 +801,11 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     const int m_max = d.precision == CB_FP64 || n > 8 * 512 ? 16 : 8;
     const int lcap = d.precision == CB_FP64 ? 1024 : 512;
     p.segs.resize(1);
-    // unit-stride lines: generalized PCR interiors on uniform lanes,
-    // elimination on general ones (measured faster each), unless asked
+    // unit-stride lines: generalized PCR interiors on uniform FP64 lanes,
+    // elimination on general ones and wherever available in FP32 (its three
+    // solves make the lane work count: penta +10 %), unless asked
     cb_status s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X,
-                                m_max, d.interior ? d.interior : 4, lcap);
+                                m_max, d.interior ? d.interior : (d.precision == CB_FP64 ? 4 : 3), lcap);
     if (s != CB_OK && d.interior == 0)
       s = build_segment(n, R, cyclic, per_row, line_coef, d.rows_per_lane, p.segs[0], msg, 0, PREF_X, m_max, 1,
                         lcap);
