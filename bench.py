@@ -342,7 +342,7 @@ def mode_serve(args):
     return {"metric": "served p50/p99 latency and GDOF/s", "runs": res,
             "saturation_gdofs": round(max(r["gdofs"] for r in res), 2), "fp64_at_highest_rate": fp64,
             "config": {"workload": "Poisson stream, sides log-uniform [32,1024], <= %.2g points, "
-                                   "tri6/penta10, FP32+refinement(2)" % args.max_points}}
+                                   "tri6/penta10, FP32+refinement (automatic count: 1 tri6, 2 penta10)" % args.max_points}}
 
 
 def mode_copy(args):

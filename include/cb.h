@@ -75,7 +75,12 @@ typedef struct {
                             workgroups (any P, detach/reattach when P is not a
                             power of two).  0 = let the library choose (1). */
   int32_t precision;     /* cb_precision */
-  int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations (0 -> 2) */
+  int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations, 1..8, or 0:
+                            automatic, the fewest k >= 1 with
+                            (kappa 2^-24)^(k+1) <= 1e-13, kappa from the
+                            symbol of constant symmetric bands (1 for the
+                            sixth-order schemes, 2 for the tenth-order
+                            pentadiagonal one); 2 for other bands */
   int32_t rows_per_lane; /* 0 = automatic; else 4, 6, 8, 12, 16 or 32 (32:
                             uniform lanes with interior elimination only) */
   int32_t host_only;     /* 1: factorise on the host only (no device memory is
@@ -177,12 +182,18 @@ typedef struct {
  *
  * `workspace` is a caller-owned DEVICE buffer of at least
  * cb_batch_workspace_size(n_items) bytes holding the queue and work table.
- * cb_batch_build validates the items and writes the table (it waits for the
- * copy to finish).  cb_batch_launch enqueues the persistent kernels only: it
- * allocates nothing, copies nothing and leaves the queue reset when it
- * finishes, so it may be captured in a HIP graph and replayed.  Launches
- * that share a workspace must not overlap in time.  `max_ctas` caps the
- * resident workgroups (0 = as many as fit on the device at once). */
+ * cb_batch_build validates the items and enqueues the upload of the table on
+ * `stream` from a pinned host buffer the library keeps per workspace; it does
+ * not wait for the upload (only for the workspace's previous one), so the
+ * workspace must not be in use by a launch on another stream.
+ * cb_batch_launch enqueues the persistent kernels only: it allocates
+ * nothing, copies nothing and leaves the queue reset when it finishes, so it
+ * may be captured in a HIP graph and replayed.  Launched on a stream other
+ * than the build's, it first makes that stream wait for the upload (while
+ * such a stream is being captured, the calling thread waits for it instead).
+ * Launches that share a
+ * workspace must not overlap in time.  `max_ctas` caps the resident
+ * workgroups (0 = as many as fit on the device at once). */
 size_t cb_batch_workspace_size(int32_t n_items);
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace,
                          size_t workspace_bytes, void *stream);

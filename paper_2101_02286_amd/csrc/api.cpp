@@ -30,8 +30,19 @@ struct BatchLaunch {
   size_t hdr_off, items_off, lds;
   int threads;
 };
+// Per workspace: its launches, the pinned host copy its table is uploaded
+// from, and the event recorded on the build stream after that upload.
+struct BatchState {
+  std::vector<BatchLaunch> launches;
+  hipStream_t stream = nullptr;
+  hipEvent_t copied = nullptr;
+  char *pinned = nullptr;
+  size_t cap = 0;
+};
 std::mutex g_batch_mu;
-std::map<void *, std::vector<BatchLaunch>> g_batch_sel;
+std::map<void *, BatchState> g_batch;
+// workspaces remembered before finished ones are forgotten
+constexpr size_t kBatchKeep = 256;
 
 // batch workspace layout: kBatchHdrBytes per class header (at most one class
 // per item), then the work table from a 256-byte boundary
@@ -734,26 +745,91 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
                         batch_items_offset(n_items) + (slot - cls[c].members.size()) * sizeof(BatchItemDev),
                         cls[c].lds, cls[c].threads});
   }
+  // The table goes up from a pinned buffer kept per workspace, in stream
+  // order, without waiting on the host: a serving loop keeps admitting work
+  // while earlier batches run.  The buffer is rewritten only after its
+  // previous upload has finished.
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "cb_batch_build: copy");
   std::lock_guard<std::mutex> lk(g_batch_mu);
-  g_batch_sel[workspace] = std::move(launches);
+  if (g_batch.size() >= kBatchKeep && !g_batch.count(workspace)) {
+    for (auto it = g_batch.begin(); it != g_batch.end();) {
+      if (it->second.copied && hipEventQuery(it->second.copied) == hipSuccess) {
+        (void)hipEventDestroy(it->second.copied);
+        if (it->second.pinned) (void)hipHostFree(it->second.pinned);
+        it = g_batch.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  BatchState &bs = g_batch[workspace];
+  hipError_t e = hipSuccess;
+  if (bs.copied) e = hipEventSynchronize(bs.copied);
+  else e = hipEventCreateWithFlags(&bs.copied, hipEventDisableTiming);
+  if (e == hipSuccess && bs.cap < host.size()) {
+    if (bs.pinned) e = hipHostFree(bs.pinned);
+    bs.pinned = nullptr;
+    bs.cap = 0;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&bs.pinned), host.size(), hipHostMallocDefault);
+    if (e == hipSuccess) bs.cap = host.size();
+  }
+  if (e != hipSuccess) {  // forget the workspace: its launches must not run on a stale table
+    if (bs.copied) (void)hipEventDestroy(bs.copied);
+    if (bs.pinned) (void)hipHostFree(bs.pinned);
+    g_batch.erase(workspace);
+    return hip_fail(e, "cb_batch_build: staging buffer");
+  }
+  std::memcpy(bs.pinned, host.data(), host.size());
+  e = hipMemcpyAsync(workspace, bs.pinned, host.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(bs.copied, st);
+  if (e != hipSuccess) {
+    bs.launches.clear();
+    return hip_fail(e, "cb_batch_build: copy");
+  }
+  bs.stream = st;
+  bs.launches = std::move(launches);
   return CB_OK;
 }
 
 cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace is NULL");
   std::vector<BatchLaunch> ls;
+  hipStream_t built_on = nullptr;
+  hipEvent_t copied = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    auto itr = g_batch_sel.find(workspace);
-    if (itr == g_batch_sel.end()) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace was not built");
-    ls = itr->second;
+    auto itr = g_batch.find(workspace);
+    if (itr == g_batch.end() || itr->second.launches.empty())
+      return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace was not built");
+    ls = itr->second.launches;
+    built_on = itr->second.stream;
+    copied = itr->second.copied;
+  }
+  const hipStream_t ls_stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (ls_stream != built_on) {
+    // the table upload was enqueued on another stream: wait for it on the
+    // device; a stream being captured cannot wait for work outside the
+    // capture, so there the host waits, with this thread's capture mode
+    // relaxed for that call
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(ls_stream, &cs);
+    if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: capture status");
+    if (cs == hipStreamCaptureStatusNone) {
+      e = hipStreamWaitEvent(ls_stream, copied, 0);
+    } else {
+      hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+      e = hipThreadExchangeStreamCaptureMode(&mode);
+      if (e == hipSuccess) {
+        e = hipEventSynchronize(copied);
+        const hipError_t e2 = hipThreadExchangeStreamCaptureMode(&mode);  // restore
+        if (e == hipSuccess) e = e2;
+      }
+    }
+    if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: waiting for the table upload");
   }
   int dev = 0, ncu = 0;
-  hipError_t e = hipGetDevice(&dev);
+  e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: device query");
   for (const BatchLaunch &l : ls) {

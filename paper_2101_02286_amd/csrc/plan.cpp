@@ -727,6 +727,47 @@ cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
 }  // namespace
 
 // ------------------------------------------------------------------- plan --
+// Refinement count when the caller leaves it to the library.  The FP32
+// reduction returns x with relative error about kappa(A) u (u = 2^-24), and
+// each FP64-residual refinement step multiplies the error by about the same
+// factor, since its correction solve has that relative error (the classical
+// analysis of mixed-precision iterative refinement); k steps leave about
+// (kappa u)^(k+1).  The count is the smallest k >= 1 with
+// (kappa u)^(k+1) <= 1e-13, ten times below the 1e-12 target.  kappa comes
+// from the symbol f(t) = a_0 + 2 sum_j a_j cos(j t) of constant symmetric
+// bands: its values at t = 2 pi k / n are the eigenvalues of the cyclic
+// matrix, and its range holds the spectrum of the acyclic one.  Per-row or
+// unsymmetric bands, and symbols that change sign, take 2 steps.
+int auto_refine_iters(const cb_plan_desc &d) {
+  const int R = d.r, n = d.n;
+  if (d.per_row) return 2;
+  double scale = 0.0;
+  for (int o = 0; o <= 2 * R; ++o) scale = std::max(scale, std::fabs(d.bands[o]));
+  for (int j = 1; j <= R; ++j)
+    if (std::fabs(d.bands[R - j] - d.bands[R + j]) > 1e-15 * scale) return 2;
+  const double two_pi = 6.283185307179586476925287;
+  const bool exact = d.cyclic && n <= 65536;
+  const int np = exact ? n : 65536;
+  double fmin = INFINITY, fmax = -INFINITY;
+  for (int k = 0; k <= np; ++k) {  // k = np repeats t = 0 (the cyclic case) or reaches t = pi
+    const double t = exact ? two_pi * (k % np) / np : two_pi * 0.5 * k / np;
+    double f = d.bands[R];
+    for (int j = 1; j <= R; ++j) f += 2.0 * d.bands[R + j] * std::cos(j * t);
+    fmin = std::min(fmin, f);
+    fmax = std::max(fmax, f);
+  }
+  if (!(fmin > 0.0 || fmax < 0.0)) return 2;
+  const double ku = std::max(std::fabs(fmin), std::fabs(fmax)) / std::min(std::fabs(fmin), std::fabs(fmax)) *
+                    5.9604644775390625e-8;
+  double e = ku * ku;
+  int k = 1;
+  while (e > 1e-13 && k < 8) {
+    e *= ku;
+    ++k;
+  }
+  return k;
+}
+
 cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   if (d.r < 1 || d.r > 2) {
     msg = "r must be 1 (tridiagonal) or 2 (pentadiagonal)";
@@ -768,7 +809,7 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   p.n = n;
   p.P = P;
   p.precision = d.precision;
-  p.refine_iters = d.precision == CB_FP32_REFINE ? (d.refine_iters > 0 ? d.refine_iters : 2) : 0;
+  p.refine_iters = d.precision == CB_FP32_REFINE ? (d.refine_iters > 0 ? d.refine_iters : auto_refine_iters(d)) : 0;
   if (p.refine_iters > 8) {
     msg = "at most 8 refinement iterations";
     return CB_ERR_INVALID_ARG;

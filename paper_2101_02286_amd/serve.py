@@ -163,7 +163,7 @@ def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_point
 class GpuExecutor:
     """Runs request groups as one persistent batched launch per stream slot."""
 
-    def __init__(self, slots=8, precision="fp32_refine", refine_iters=2, rows_per_lane=0, device="cuda:0",
+    def __init__(self, slots=8, precision="fp32_refine", refine_iters=0, rows_per_lane=0, device="cuda:0",
                  on_result=None):
         import torch
         from . import cb

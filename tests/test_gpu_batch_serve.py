@@ -176,6 +176,61 @@ def test_graph_replay_of_batched_launch(gpu):
             assert torch.equal(it[3], e), rep
 
 
+def test_batch_table_upload_streams(gpu):
+    """The work table goes up asynchronously on the build stream: a launch on
+    another stream waits for it (on the host while that stream is being
+    captured), and a rebuilt workspace carries the new table."""
+    f, _ = synth.random_modes((20, 36, 28), seed=9)
+    fd = f.to(gpu)
+    sets = []
+    for scheme, bands in (("tri6", TRI), ("penta10", PENTA)):
+        items, refs = [], []
+        for axis in range(3):
+            n = fd.shape[2 - axis]
+            lo, c = stencil_for(scheme, n)
+            items.append((cb.Plan(bands, n), cb.Stencil(lo, c), fd, torch.empty_like(fd), axis))
+            refs.append(oracle.apply_axis(f.numpy(), axis, bands, lo, c))
+        sets.append((items, refs))
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ws = None
+    for items, refs in sets + sets:  # the second round rebuilds the same workspace
+        if ws is None:
+            ws = batch(items, stream=sa)
+        else:
+            arr = (cb.BatchItem * len(items))()
+            for i, (plan, st, x, out, axis) in enumerate(items):
+                arr[i].plan, arr[i].stencil, arr[i].grid = plan.h, cb.ctypes.pointer(st.c), cb.grid_of(x)
+                arr[i].axis, arr[i].inp, arr[i].out = axis, x.data_ptr(), out.data_ptr()
+            cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                              cb.ctypes.c_void_p(sa.cuda_stream)))
+        launch(ws, stream=sb)
+        sb.synchronize()
+        for it, ref in zip(items, refs):
+            assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
+            it[3].zero_()
+        torch.cuda.synchronize()
+    # captured on a third stream after a rebuild on the first
+    items, refs = sets[0]
+    arr = (cb.BatchItem * len(items))()
+    for i, (plan, st, x, out, axis) in enumerate(items):
+        arr[i].plan, arr[i].stencil, arr[i].grid = plan.h, cb.ctypes.pointer(st.c), cb.grid_of(x)
+        arr[i].axis, arr[i].inp, arr[i].out = axis, x.data_ptr(), out.data_ptr()
+    cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      cb.ctypes.c_void_p(sa.cuda_stream)))
+    sc = torch.cuda.Stream()  # the capture waits for the upload on the host
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=sc):
+        launch(ws, stream=sc)
+    for rep in range(3):
+        for it in items:
+            it[3].fill_(float(rep))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for it, ref in zip(items, refs):
+            assert relerr(it[3].cpu().numpy(), ref) <= 1e-12, rep
+
+
 def test_server_results_same_alone_and_in_mix(gpu):
     results = {}
 

@@ -408,3 +408,27 @@ def test_tile_orders(gpu, axis, n, prec):
     ref = oracle.apply_axis(f.numpy(), axis, TRI, lo, c)
     assert relerr(outs[1], ref) <= 1e-12
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("scheme", ["deriv6", "deriv10", "interp6"])
+@pytest.mark.parametrize("n", [64, 613, 2048, 8192])
+def test_automatic_refinement_count_meets_tolerance(gpu, axis, scheme, n):
+    """FP32 + refinement with the library's own iteration count (one for the
+    sixth-order schemes, two for the tenth-order one) meets 1e-12, up to
+    lines of 8192 rows."""
+    bands = {"deriv6": TRI, "deriv10": PENTA, "interp6": INTERP}[scheme]
+    plan = cb.Plan(bands, n, precision="fp32_refine")
+    assert plan.info()["refine_iters"] == (2 if scheme == "deriv10" else 1)
+    other = (4, 6) if n >= 2048 else (8, 12)
+    shape = shape_with(axis, n, other)
+    if scheme == "interp6":
+        b = synth.random_uniform(shape, seed=n + axis)
+        out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        ref = oracle.solve_axis(b.numpy(), axis, bands)
+    else:
+        f, _ = synth.random_modes(shape, seed=n + 3 * axis)
+        lo, c = deriv_stencil(schemes.DERIV6 if scheme == "deriv6" else schemes.DERIV10, n)
+        out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+        ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
+    assert relerr(out, ref) <= 1e-12

@@ -240,3 +240,36 @@ def test_long_lines_split_strided_launches():
     assert (i["partitions"], i["partitions_strided"]) == (1, 8)
     assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
     assert cb.Plan(tri, 8192, rows_per_lane=16, host_only=True).info()["partitions_strided"] == 1
+
+
+def test_automatic_refinement_count():
+    """CB_FP32_REFINE with refine_iters 0: the fewest k >= 1 with
+    (kappa u)^(k+1) <= 1e-13, u = 2^-24, kappa the ratio of the extreme values
+    of the symbol a0 + 2 sum a_j cos(j t) (cyclic: the eigenvalues)."""
+    u = 2.0 ** -24
+
+    def expect(bands, n, cyclic):
+        r = (len(bands) - 1) // 2
+        t = 2 * np.pi * np.arange(n) / n if cyclic else np.linspace(0, np.pi, 65537)
+        f = bands[r] + sum(2 * bands[r + j] * np.cos(j * t) for j in range(1, r + 1))
+        ku = np.abs(f).max() / np.abs(f).min() * u
+        k = 1
+        while ku ** (k + 1) > 1e-13 and k < 8:
+            k += 1
+        return k
+
+    tri = [1 / 3, 1.0, 1 / 3]                      # kappa 5: (5u)^2 = 8.9e-14
+    penta = [1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20]    # kappa 21: (21u)^2 = 1.6e-12
+    interp = [0.3, 1.0, 0.3]                       # kappa 4
+    weak = [0.49, 1.0, 0.49]                       # kappa 99: (99u)^2 = 3.5e-11
+    for bands, n, cyc, want in ((tri, 512, 1, 1), (tri, 613, 0, 1), (penta, 512, 1, 2), (penta, 100, 0, 2),
+                                (interp, 256, 1, 1), (weak, 512, 1, 2)):
+        assert expect(bands, n, cyc) == want
+        p = cb.Plan(bands, n, cyclic=bool(cyc), precision="fp32_refine", host_only=True)
+        assert p.info()["refine_iters"] == want, (bands, n, cyc)
+    # explicit counts are kept; per-row and unsymmetric bands take 2
+    assert cb.Plan(tri, 512, precision="fp32_refine", refine_iters=3, host_only=True).info()["refine_iters"] == 3
+    rows = np.tile(np.array(tri), (64, 1))
+    assert cb.Plan(rows, 64, per_row=True, precision="fp32_refine", host_only=True).info()["refine_iters"] == 2
+    assert cb.Plan([0.2, 1.0, 0.3], 64, precision="fp32_refine", host_only=True).info()["refine_iters"] == 2
+    assert cb.Plan(tri, 512, precision="fp64", host_only=True).info()["refine_iters"] == 0
