@@ -73,7 +73,9 @@ typedef struct {
   int32_t partitions;    /* P >= 1 workgroup partitions per line (Sec. 3 p);
                             P > 1 solves the reduced P-block system across
                             workgroups (any P, detach/reattach when P is not a
-                            power of two).  0 = let the library choose (1). */
+                            power of two).  0 = let the library choose: 1
+                            while a line fits one workgroup (n <= 16384),
+                            else, in FP64, ceil(n / 1024) up to 64. */
   int32_t precision;     /* cb_precision */
   int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations, 1..8, or 0:
                             automatic, the fewest k >= 1 with

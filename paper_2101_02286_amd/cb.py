@@ -112,7 +112,7 @@ class Stencil:
 class Plan:
     """Pre-factorised compact banded matrix (cb_plan)."""
 
-    def __init__(self, bands, n, cyclic=True, partitions=1, precision="fp64", refine_iters=0,
+    def __init__(self, bands, n, cyclic=True, partitions=0, precision="fp64", refine_iters=0,
                  rows_per_lane=0, per_row=False, host_only=False, lines_per_wg=0, block_barriers=0,
                  x_staging=0, interior=0, tile_order=0):
         import numpy as np

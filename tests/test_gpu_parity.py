@@ -432,3 +432,17 @@ def test_automatic_refinement_count_meets_tolerance(gpu, axis, scheme, n):
         out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
         ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
     assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("bands,n", [(TRI, 32768), (PENTA, 20000)])
+def test_lines_longer_than_a_workgroup(gpu, axis, bands, n):
+    """Default plans for lines longer than 16384 rows split them into
+    workgroup partitions by themselves (fused derivative, a few lines)."""
+    plan = cb.Plan(bands, n)
+    assert plan.info()["partitions"] == (n + 1023) // 1024
+    f, _ = synth.random_modes(shape_with(axis, n, (3, 2)), seed=n + axis)
+    lo, c = deriv_stencil(schemes.DERIV6 if bands is TRI else schemes.DERIV10, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), axis, bands, lo, c)
+    assert relerr(out, ref) <= 1e-12

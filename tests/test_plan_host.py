@@ -273,3 +273,16 @@ def test_automatic_refinement_count():
     assert cb.Plan(rows, 64, per_row=True, precision="fp32_refine", host_only=True).info()["refine_iters"] == 2
     assert cb.Plan([0.2, 1.0, 0.3], 64, precision="fp32_refine", host_only=True).info()["refine_iters"] == 2
     assert cb.Plan(tri, 512, precision="fp64", host_only=True).info()["refine_iters"] == 0
+
+
+def test_automatic_partition_count():
+    """partitions 0: one workgroup per line up to 16384 rows, else FP64 lines
+    in ceil(n / 1024) workgroup partitions (at most 64); FP32 lines longer
+    than a workgroup are rejected."""
+    tri = [1 / 3, 1.0, 1 / 3]
+    for n, want in ((512, 1), (16384, 1), (16385, 17), (32768, 32), (50000, 49), (100000, 64)):
+        info = cb.Plan(tri, n, host_only=True).info()
+        assert info["partitions"] == want, n
+    assert cb.Plan(tri, 32768, partitions=4, host_only=True).info()["partitions"] == 4
+    with pytest.raises(cb.CbError):
+        cb.Plan(tri, 32768, precision="fp32_refine", host_only=True)
