@@ -372,7 +372,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
   const int Q = st ? 3 : 0;
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
-  const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q);
+  const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q, p.segs[0].ilu != 0);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
   const int L = p.L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);

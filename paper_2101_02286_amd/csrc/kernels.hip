@@ -58,7 +58,7 @@ __device__ __forceinline__ int tile_at(int e) {
   return e + e / M;
 }
 
-template <int R, int M, int MODE, int Q, bool ADJ>
+template <int R, int M, int MODE, int Q, bool ADJ, bool ILU>
 __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
                                                   int &start, int &m, double *coef_lds, double *tb,
@@ -166,9 +166,9 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     }
   }
   if (a.coef_lds)
-    solve_segment<R, M, double, false, CSRC_LDS>(v, sg, p, type, m, xc, coef_lds);
+    solve_segment<R, M, double, false, CSRC_LDS, ILU>(v, sg, p, type, m, xc, coef_lds);
   else
-    solve_segment<R, M, double, false, CSRC_GLOBAL>(v, sg, p, type, m, xc);
+    solve_segment<R, M, double, false, CSRC_GLOBAL, ILU>(v, sg, p, type, m, xc);
 }
 
 // Workgroup bound of the partitioned kernels: unit-stride 16-row instances
@@ -178,7 +178,7 @@ constexpr int wg_max_threads() {
   return (MODE == MODE_X && M > 8) ? 512 : 1024;
 }
 
-template <int R, int M, int MODE, int Q>
+template <int R, int M, int MODE, int Q, bool ILU>
 __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgArgs a) {
   extern __shared__ double smem[];
   LanePos p;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgAr
   double v[M];
   int start, m;
   const double none[R] = {};
-  wg_solve_interior<R, M, MODE, Q, false>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a,
+  wg_solve_interior<R, M, MODE, Q, false, ILU>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a,
                                           a.stage_x ? smem + a.stage_off_a + (size_t)p.li * a.stage_pitch : nullptr,
                                           none, none);
   if (!active) return;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
 
 // Phase C: x_i = D_i^{-1}[b_i - L_i x~_i - U_i x~_{i+1}] (Eq. (9), equal to
 // the back-substitution of Eq. (22)) from the interface values of phase B.
-template <int R, int M, int MODE, int Q>
+template <int R, int M, int MODE, int Q, bool ILU>
 __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgArgs a) {
   extern __shared__ double smem[];
   constexpr int RS = Q > R ? 2 * Q : 2 * R;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
   double v[M];
   int start, m;
   double *tb = a.stage_x ? smem + a.stage_off_c + (size_t)p.li * a.stage_pitch : nullptr;
-  wg_solve_interior<R, M, MODE, Q, true>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c, tb, xi,
+  wg_solve_interior<R, M, MODE, Q, true, ILU>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c, tb, xi,
                                          xi1);
   const int64_t seg0 = a.wg_start[part] + R;
   if (MODE == MODE_X && tb != nullptr) {
@@ -414,18 +414,19 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
   return nullptr;
 }
 
-#define CB_WG_INST(R, M, MODE, Q)                                                                      \
-  {R, M, MODE, Q, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, M, MODE, Q>,                       \
-   (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q>}
-#define CB_WG_Q(R, M, MODE) CB_WG_INST(R, M, MODE, 0), CB_WG_INST(R, M, MODE, 3)
+#define CB_WG_INST(R, M, MODE, Q, ILU)                                                                 \
+  {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, M, MODE, Q, ILU>,             \
+   (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q, ILU>}
+#define CB_WG_I(R, M, MODE, Q) CB_WG_INST(R, M, MODE, Q, false), CB_WG_INST(R, M, MODE, Q, true)
+#define CB_WG_Q(R, M, MODE) CB_WG_I(R, M, MODE, 0), CB_WG_I(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {
     CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),
     CB_WG_Q(1, 16, MODE_X), CB_WG_Q(1, 16, MODE_S), CB_WG_Q(2, 16, MODE_X), CB_WG_Q(2, 16, MODE_S),
 };
 
-const WgKernel *find_wg_kernel(int R, int M, int mode, int Q) {
+const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu) {
   for (const auto &k : kWgKernels)
-    if (k.R == R && k.M == M && k.mode == mode && k.Q == Q) return &k;
+    if (k.R == R && k.M == M && k.mode == mode && k.Q == Q && k.ilu == ilu) return &k;
   return nullptr;
 }
 

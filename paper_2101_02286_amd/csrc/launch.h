@@ -82,6 +82,7 @@ struct LineKernel {
 };
 struct WgKernel {
   int R, M, mode, Q;
+  bool ilu;                        // lane interiors by banded elimination
   int max_threads;                 // workgroup size bound of phases A and C
   const void *fn_a, *fn_b, *fn_c;  // phases A (interiors), B (reduced system), C (back-substitution)
 };
@@ -109,7 +110,7 @@ static_assert(sizeof(BatchHdr) <= 64, "batch queue header must fit its 64-byte s
 
 const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu);
 const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode);
-const WgKernel *find_wg_kernel(int R, int M, int mode, int Q);
+const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu);
 const void *stencil_kernel();
 
 }  // namespace cb

@@ -865,7 +865,8 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       // FP64 strided lines on uniform lanes take 32 rows per lane when the
       // lane count allows (32 adjacent lines per workgroup, 256-byte segments)
       // (FP32: up to 12 rows per lane, measured faster than 6 at n = 384)
-      const int m_max_s = d.precision == CB_FP64 ? 32 : std::max(m_max, 12);
+      // (32-row lanes always eliminate: not when generalized PCR is asked for)
+      const int m_max_s = d.precision == CB_FP64 ? (d.interior == 1 ? 16 : 32) : std::max(m_max, 12);
       s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max_s,
                         d.interior ? d.interior : 3, lcap);
       if (s != CB_OK && d.interior == 0)
@@ -894,12 +895,9 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     }
     return CB_OK;
   }
-  if (d.interior == 2) {
-    msg = "interior elimination is available for one-partition plans";
-    return CB_ERR_UNSUPPORTED;
-  }
   // P > 1: workgroup partitions, each with R interface rows and an interior
-  // segment D_i solved by the lane-level scheme.
+  // segment D_i solved by the lane-level scheme (banded elimination unless
+  // asked otherwise or a pivot vanishes: generalized PCR then).
   p.wg_start.assign(P + 1, 0);
   const int base = n / P, extra = n % P;
   for (int i = 0; i < P; ++i) p.wg_start[i + 1] = p.wg_start[i] + base + (i < extra ? 1 : 0);
@@ -919,13 +917,20 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     }
   }
   p.segs.resize(P);
-  for (int i = 0; i < P; ++i) {
-    const int g0 = p.wg_start[i] + R;
-    const int S = p.wg_start[i + 1] - g0;
-    auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
-    s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg, PREF_S, 16, d.interior);
-    if (s != CB_OK) return s;
+  for (int pass = 0; pass < 2; ++pass) {
+    // one kernel serves all partitions: every segment takes the same interior
+    // solve (elimination for all, or generalized PCR for all)
+    const int interior = d.interior ? d.interior : (pass == 0 ? 2 : 1);
+    s = CB_OK;
+    for (int i = 0; i < P && s == CB_OK; ++i) {
+      const int g0 = p.wg_start[i] + R;
+      const int S = p.wg_start[i + 1] - g0;
+      auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
+      s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg, PREF_S, 16, interior);
+    }
+    if (s == CB_OK || d.interior) break;
   }
+  if (s != CB_OK) return s;
   p.M = M;
   p.L = p.segs[0].L;
   for (int i = 1; i < P; ++i)

@@ -208,7 +208,20 @@ def test_interior_elimination_rejected_where_unsupported():
     with pytest.raises(cb.CbError):
         cb.Plan([1 / 3, 1, 1 / 3], 512, rows_per_lane=4, interior=2, host_only=True)
     with pytest.raises(cb.CbError):
-        cb.Plan([1 / 3, 1, 1 / 3], 8192, partitions=16, interior=2, host_only=True)
+        cb.Plan([1 / 3, 1, 1 / 3], 8192, partitions=16, rows_per_lane=4, interior=2, host_only=True)
+
+
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("n,P,interior", [(8192, 16, 0), (8192, 16, 1), (8192, 16, 2), (1000, 3, 0), (4099, 7, 0)])
+def test_partition_interiors(name, n, P, interior):
+    """Workgroup partitions solve their lane interiors by elimination by
+    default (PCR on request); either way the plan reproduces the oracle."""
+    bands = _bands(name)
+    p = cb.Plan(bands, n, partitions=P, interior=interior, host_only=True)
+    assert p.info()["interior_elimination"] == (0 if interior == 1 else 1)
+    b = np.random.default_rng(n + P).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands)
+    assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_tuner_searches_partition_counts_for_long_lines():
@@ -286,3 +299,14 @@ def test_automatic_partition_count():
     assert cb.Plan(tri, 32768, partitions=4, host_only=True).info()["partitions"] == 4
     with pytest.raises(cb.CbError):
         cb.Plan(tri, 32768, precision="fp32_refine", host_only=True)
+
+
+@pytest.mark.parametrize("n", [512, 8192])
+def test_generalized_pcr_on_request_without_row_count(n):
+    """interior = 1 without rows_per_lane: every layout of the plan uses
+    generalized PCR (strided lanes stop at 16 rows, since 32-row lanes only
+    eliminate)."""
+    p = cb.Plan([1 / 3, 1.0, 1 / 3], n, interior=1, host_only=True)
+    info = p.info()
+    assert info["interior_elimination"] == 0 and info["interior_elimination_strided"] == 0
+    assert info["rows_per_lane_strided"] <= 16
