@@ -370,7 +370,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
 cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                     hipStream_t stream) {
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
-  const int Q = st ? 3 : 0;
+  const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;  // stencil half-width of the kernel
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
   const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q, p.segs[0].ilu != 0);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");

@@ -187,10 +187,10 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgAr
   wg_setup<R, M, MODE>(a, p, line, active, base);
   Xchg xc{smem, (Q > R ? 2 * Q : 2 * R), (int)blockDim.x, 0, true};
   const int part = blockIdx.y;
-  // inputs of the partition's interface rows g0..g0+R-1 (with the +-3
+  // inputs of the partition's interface rows g0..g0+R-1 (with the +-Q
   // stencil neighbours), read before the interior solve so their latency
   // overlaps it
-  constexpr int QI = Q > 0 ? 3 : 0;
+  constexpr int QI = Q;
   double iv[R + 2 * QI];
   const int64_t g0 = a.wg_start[part];
 #pragma unroll
@@ -214,7 +214,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgAr
       if constexpr (Q > 0) {  // stencil at the partition's interface row g0 + c
         bt = 0.0;
 #pragma unroll
-        for (int q = -3; q <= 3; ++q) bt += a.stc[q + 3] * iv[c + q + QI];
+        for (int q = -QI; q <= QI; ++q) bt += a.stc[q + 3] * iv[c + q + QI];
       } else {
         bt = iv[c];
       }
@@ -418,7 +418,7 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
   {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, M, MODE, Q, ILU>,             \
    (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q, ILU>}
 #define CB_WG_I(R, M, MODE, Q) CB_WG_INST(R, M, MODE, Q, false), CB_WG_INST(R, M, MODE, Q, true)
-#define CB_WG_Q(R, M, MODE) CB_WG_I(R, M, MODE, 0), CB_WG_I(R, M, MODE, 3)
+#define CB_WG_Q(R, M, MODE) CB_WG_I(R, M, MODE, 0), CB_WG_I(R, M, MODE, 2), CB_WG_I(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {
     CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),
     CB_WG_Q(1, 16, MODE_X), CB_WG_Q(1, 16, MODE_S), CB_WG_Q(2, 16, MODE_X), CB_WG_Q(2, 16, MODE_S),
