@@ -195,7 +195,9 @@ typedef struct {
  * such a stream is being captured, the calling thread waits for it instead).
  * Launches that share a
  * workspace must not overlap in time.  `max_ctas` caps the resident
- * workgroups (0 = as many as fit on the device at once). */
+ * workgroups (0 = as many as fit on the device at once); a negative value
+ * launches one workgroup per tile instead of the persistent queue (tiles in
+ * the XCD-grouped order of single strided launches). */
 size_t cb_batch_workspace_size(int32_t n_items);
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace,
                          size_t workspace_bytes, void *stream);

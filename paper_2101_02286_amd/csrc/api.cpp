@@ -29,6 +29,7 @@ struct BatchLaunch {
   const void *fn;
   size_t hdr_off, items_off, lds;
   int threads;
+  int64_t tiles;
 };
 // Per workspace: its launches, the pinned host copy its table is uploaded
 // from, and the event recorded on the build stream after that upload.
@@ -740,10 +741,11 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     std::memset(&h, 0, sizeof(h));
     h.n_items = (int)cls[c].members.size();
     h.total_tiles = tiles;
+    h.xcds = xcd_count();
     std::memcpy(host.data() + c * kBatchHdrBytes, &h, sizeof(h));
     launches.push_back({cls[c].fn, c * kBatchHdrBytes,
                         batch_items_offset(n_items) + (slot - cls[c].members.size()) * sizeof(BatchItemDev),
-                        cls[c].lds, cls[c].threads});
+                        cls[c].lds, cls[c].threads, tiles});
   }
   // The table goes up from a pinned buffer kept per workspace, in stream
   // order, without waiting on the host: a serving loop keeps admitting work
@@ -838,9 +840,15 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: occupancy query");
     int ctas = std::max(1, ncu * std::max(per_cu, 1));
     if (max_ctas > 0) ctas = std::min(ctas, (int)max_ctas);
+    int per_tile = 0;
+    if (max_ctas < 0) {  // one workgroup per tile instead of the persistent queue
+      if (l.tiles > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "cb_batch_launch: too many tiles for one grid");
+      per_tile = 1;
+      ctas = (int)std::max<int64_t>(l.tiles, 1);
+    }
     BatchHdr *hdr = reinterpret_cast<BatchHdr *>(static_cast<char *>(workspace) + l.hdr_off);
     const BatchItemDev *its = reinterpret_cast<const BatchItemDev *>(static_cast<char *>(workspace) + l.items_off);
-    void *args[] = {&hdr, &its};
+    void *args[] = {&hdr, &its, &per_tile};
     e = hipLaunchKernel(l.fn, dim3(ctas), dim3(l.threads), args, l.lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
   }

@@ -290,11 +290,31 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_li
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, bool UNI, bool ILU, int MODE>
 __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
-                                                                               const BatchItemDev *items) {
+                                                                               const BatchItemDev *items,
+                                                                               int per_tile) {
   extern __shared__ double smem[];
   __shared__ int64_t s_tile;
   const int64_t total = hdr->total_tiles;
   const int nitems = hdr->n_items;
+  if (per_tile) {
+    // one workgroup per tile (no queue), tiles in XCD-grouped order as in
+    // k_line: XCD j takes the j-th contiguous range
+    uint32_t t = blockIdx.x;
+    if (hdr->xcds > 1) {
+      const uint32_t X = (uint32_t)hdr->xcds, G = gridDim.x, q = G / X, rem = G % X;
+      const uint32_t j = t % X, s = t / X;
+      t = j * q + (j < rem ? j : rem) + s;
+    }
+    if ((int64_t)t >= total) return;
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= (int64_t)t) lo = mid; else hi = mid - 1;
+    }
+    const BatchItemDev &it = items[lo];
+    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, (int64_t)t - it.tile_begin, smem);
+    return;
+  }
   for (;;) {
     if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&hdr->next_tile, 1ull);
     __syncthreads();

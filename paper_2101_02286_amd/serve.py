@@ -4,7 +4,7 @@ Requests (a 3D periodic grid, an axis, a scheme) arrive over time.  The
 server keeps factorised plans on the device (one per scheme and line length),
 admits arrived requests in FIFO order while their device memory fits the HBM
 budget, and launches every group of admitted-but-not-started requests as ONE
-persistent batched kernel (cb_solve_batched) on a free stream slot -- while
+batched launch (cb_solve_batched: one kernel per kernel class) on a free stream slot -- while
 earlier batches are still running on other slots.  Finished batches release
 their memory at once, so waiting requests are admitted as slots and memory
 free up.  Latency = completion - arrival.
@@ -161,7 +161,7 @@ def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_point
 
 
 class GpuExecutor:
-    """Runs request groups as one persistent batched launch per stream slot."""
+    """Runs request groups as one batched launch per stream slot."""
 
     def __init__(self, slots=8, precision="fp32_refine", refine_iters=0, rows_per_lane=0, device="cuda:0",
                  on_result=None):
@@ -192,7 +192,7 @@ class GpuExecutor:
         return self.plans[key], self.stencils[key]
 
     def group_key(self, r):
-        # a batched launch takes any mix of plans (one persistent kernel per
+        # a batched launch takes any mix of plans (one kernel launch per
         # kernel class), so every request may join every batch
         return 0
 
@@ -225,7 +225,8 @@ class GpuExecutor:
         if ws is None or ws.numel() < need:
             ws = torch.empty(max(need, 1 << 16), dtype=torch.uint8, device=self.device)
             self.ws[slot] = ws
-        cb._check(cb.lib().cb_solve_batched(items, len(reqs), cb.ctypes.c_void_p(ws.data_ptr()), ws.numel(), 0,
+        # one workgroup per tile (measured faster than the persistent queue)
+        cb._check(cb.lib().cb_solve_batched(items, len(reqs), cb.ctypes.c_void_p(ws.data_ptr()), ws.numel(), -1,
                                             cb.ctypes.c_void_p(s.cuda_stream)))
         ev = torch.cuda.Event()
         ev.record(s)

@@ -52,8 +52,11 @@ def launch(ws, stream=None, max_ctas=0):
                                        cb.ctypes.c_void_p(s.cuda_stream)))
 
 
+@pytest.mark.parametrize("max_ctas", [7, -1])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
-def test_uneven_grids_one_launch(gpu, precision):
+def test_uneven_grids_one_launch(gpu, precision, max_ctas):
+    """Persistent queue with few workgroups (each loops over many tiles), and
+    one workgroup per tile in XCD-grouped order."""
     shapes = [(16, 16, 16), (32, 24, 40), (48, 48, 48), (96, 32, 16), (24, 128, 8), (64, 20, 36)]
     items, refs = [], []
     for gi, (nx, ny, nz) in enumerate(shapes):
@@ -67,7 +70,7 @@ def test_uneven_grids_one_launch(gpu, precision):
             items.append((plan, cb.Stencil(lo, c), fd, out, axis))
             refs.append(oracle.apply_axis(f.numpy(), axis, TRI, lo, c))
     ws = batch(items)
-    launch(ws, max_ctas=7)  # few workgroups: each loops over many tiles
+    launch(ws, max_ctas=max_ctas)
     torch.cuda.synchronize()
     for (plan, st, fd, out, axis), ref in zip(items, refs):
         assert relerr(out.cpu().numpy(), ref) <= 1e-12
@@ -125,12 +128,16 @@ def test_mixed_plans_one_batch(gpu):
             fd = b.to(gpu)
             singles.append(cb.solve(plan, fd, axis))
         items.append((plan, st, fd, torch.empty_like(fd), axis))
-    launch(batch(items), max_ctas=11)
-    torch.cuda.synchronize()
-    for (plan, st, fd, out, axis), single, ref in zip(items, singles, refs):
-        got = out.cpu().numpy()
-        assert relerr(got, ref) <= 1e-12
-        assert np.array_equal(got, single.cpu().numpy())
+    ws = batch(items)
+    for max_ctas in (11, -1):  # persistent queue, then one workgroup per tile
+        for it in items:
+            it[3].fill_(float("nan"))
+        launch(ws, max_ctas=max_ctas)
+        torch.cuda.synchronize()
+        for (plan, st, fd, out, axis), single, ref in zip(items, singles, refs):
+            got = out.cpu().numpy()
+            assert relerr(got, ref) <= 1e-12
+            assert np.array_equal(got, single.cpu().numpy())
 
 
 def test_batch_with_empty_items(gpu):
@@ -149,7 +156,8 @@ def test_batch_with_empty_items(gpu):
             assert relerr(it[3].cpu().numpy(), ref) <= 1e-12
 
 
-def test_graph_replay_of_batched_launch(gpu):
+@pytest.mark.parametrize("max_ctas", [0, -1])
+def test_graph_replay_of_batched_launch(gpu, max_ctas):
     """Captured launch replayed several times with eager work in between."""
     f, _ = synth.random_modes((24, 40, 32), seed=4)
     fd = f.to(gpu)
@@ -160,12 +168,12 @@ def test_graph_replay_of_batched_launch(gpu):
         items.append((cb.Plan(TRI, n, rows_per_lane=8), cb.Stencil(lo, c), fd, torch.empty_like(fd), axis))
     s = torch.cuda.Stream()
     ws = batch(items, stream=s)
-    launch(ws, stream=s)
+    launch(ws, stream=s, max_ctas=max_ctas)
     s.synchronize()
     eager = [it[3].clone() for it in items]
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
-        launch(ws, stream=s)
+        launch(ws, stream=s, max_ctas=max_ctas)
     for rep in range(4):
         for it in items:
             it[3].fill_(float(rep))  # eager work between replays
