@@ -254,6 +254,18 @@ cb_status check_stencil(const cb_stencil *st) {
 cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                     hipStream_t stream);
 
+// Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
+// turn, so in launch order neighbouring tiles run on different XCDs):
+// automatic when row segments are narrower than a 128-byte L2 line (its
+// tiles then share lines) or rows lie at most 64 KB apart (measured: 3-4 KB
+// row strides gain 4-10 %, 1.5-2 MB ones lose 4-10 % with wide segments).
+// Returns the XCD count to group over, or 1 for launch order.
+int tile_xcds(const Plan &p, int mode, int W, int64_t rs) {
+  const bool on = mode == MODE_S && (p.desc.tile_order == 2 ||
+                                     (p.desc.tile_order == 0 && (W * 8 < 128 || rs * (int64_t)sizeof(double) <= 65536)));
+  return on ? xcd_count() : 1;
+}
+
 // --------------------------------------------------------- P = 1 launch --
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                       hipStream_t stream) {
@@ -352,15 +364,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const size_t lds = lds_of(W);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
-  // Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
-  // turn, so in launch order neighbouring tiles run on different XCDs):
-  // automatic when row segments are narrower than a 128-byte L2 line (its
-  // tiles then share lines) or rows lie at most 64 KB apart (measured: 3-4 KB
-  // row strides gain 4-10 %, 1.5-2 MB ones lose 4-10 % with wide segments)
-  const bool xcd_order =
-      mode == MODE_S && (p.desc.tile_order == 2 ||
-                         (p.desc.tile_order == 0 && (W * 8 < 128 || g.rs * (int64_t)sizeof(double) <= 65536)));
-  a.xcds = xcd_order ? xcd_count() : 1;
+  a.xcds = tile_xcds(p, mode, W, g.rs);
   void *args[] = {&a};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(NT), args, lds, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -694,6 +698,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.nudiv = make_divmagic((uint32_t)g.nu);
     a.lgL = ilog2(L);
     a.lgW = ilog2(W);
+    a.xcds = tile_xcds(p, mode, W, g.rs);  // used by one-workgroup-per-tile launches
     // lanes of a unit-stride line are adjacent threads: with L <= 64 a line
     // lies in one wavefront and its exchanges need no workgroup barrier
     a.block_sync = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 0 : 1;
@@ -741,7 +746,6 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     std::memset(&h, 0, sizeof(h));
     h.n_items = (int)cls[c].members.size();
     h.total_tiles = tiles;
-    h.xcds = xcd_count();
     std::memcpy(host.data() + c * kBatchHdrBytes, &h, sizeof(h));
     launches.push_back({cls[c].fn, c * kBatchHdrBytes,
                         batch_items_offset(n_items) + (slot - cls[c].members.size()) * sizeof(BatchItemDev),

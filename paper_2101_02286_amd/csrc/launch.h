@@ -93,8 +93,6 @@ struct BatchHdr {
   unsigned int done;             // workgroups that have left
   int n_items;
   int64_t total_tiles;
-  int xcds;                      // one-workgroup-per-tile launches: tiles in XCD-grouped order
-  int pad;
 };
 struct BatchItemDev {
   LineArgs a;

@@ -297,22 +297,24 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_ba
   const int64_t total = hdr->total_tiles;
   const int nitems = hdr->n_items;
   if (per_tile) {
-    // one workgroup per tile (no queue), tiles in XCD-grouped order as in
-    // k_line: XCD j takes the j-th contiguous range
-    uint32_t t = blockIdx.x;
-    if (hdr->xcds > 1) {
-      const uint32_t X = (uint32_t)hdr->xcds, G = gridDim.x, q = G / X, rem = G % X;
-      const uint32_t j = t % X, s = t / X;
-      t = j * q + (j < rem ? j : rem) + s;
-    }
-    if ((int64_t)t >= total) return;
+    // one workgroup per tile (no queue); within an item whose tile order is
+    // XCD-grouped (as a single launch of it would take), the workgroups of
+    // one XCD (every X-th) take one contiguous range of its tiles
+    const int64_t t = blockIdx.x;
+    if (t >= total) return;
     int lo = 0, hi = nitems - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (items[mid].tile_begin <= (int64_t)t) lo = mid; else hi = mid - 1;
+      if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
     }
     const BatchItemDev &it = items[lo];
-    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, (int64_t)t - it.tile_begin, smem);
+    int64_t local = t - it.tile_begin;
+    if (it.a.xcds > 1) {
+      const int64_t G = (lo + 1 < nitems ? items[lo + 1].tile_begin : total) - it.tile_begin;
+      const int64_t X = it.a.xcds, q = G / X, rem = G % X, j = local % X, s = local / X;
+      local = j * q + (j < rem ? j : rem) + s;
+    }
+    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, local, smem);
     return;
   }
   for (;;) {
