@@ -172,8 +172,9 @@ typedef struct {
 } cb_batch_item;
 
 /* Batched execution: the lines of many items -- uneven grids, any axes,
- * different plans -- run in persistent kernel launches that take line tiles
- * from device work queues: ONE launch per kernel class present in the batch
+ * different plans -- run in ONE kernel launch per kernel class present in the
+ * batch, either persistent (a resident grid takes line tiles from a device
+ * work queue) or with one workgroup per line tile
  * (a class is r, rows per lane, arithmetic, uniform or general lane layout,
  * interior solve and unit-stride or strided rows, as an item's plan and row
  * stride select them; a batch of plans built alike for one scheme and
@@ -188,16 +189,17 @@ typedef struct {
  * `stream` from a pinned host buffer the library keeps per workspace; it does
  * not wait for the upload (only for the workspace's previous one), so the
  * workspace must not be in use by a launch on another stream.
- * cb_batch_launch enqueues the persistent kernels only: it allocates
- * nothing, copies nothing and leaves the queue reset when it finishes, so it
- * may be captured in a HIP graph and replayed.  Launched on a stream other
+ * cb_batch_launch enqueues the kernels only: it allocates nothing, copies
+ * nothing and leaves the queue reset when it finishes, so it may be captured
+ * in a HIP graph and replayed.  Launched on a stream other
  * than the build's, it first makes that stream wait for the upload (while
  * such a stream is being captured, the calling thread waits for it instead).
  * Launches that share a
- * workspace must not overlap in time.  `max_ctas` caps the resident
- * workgroups (0 = as many as fit on the device at once); a negative value
- * launches one workgroup per tile instead of the persistent queue (tiles in
- * the XCD-grouped order of single strided launches). */
+ * workspace must not overlap in time.  `max_ctas` >= 0 selects the
+ * persistent form and caps its resident workgroups (0 = as many as fit on
+ * the device at once); a negative value launches one workgroup per tile
+ * instead (each item's tiles in the order its single launch would take;
+ * measured the faster form). */
 size_t cb_batch_workspace_size(int32_t n_items);
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace,
                          size_t workspace_bytes, void *stream);
