@@ -157,10 +157,10 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
 #pragma unroll
         for (int o = -R; o <= R; ++o) {
           const int t = sr + o;
-          // R <= 2: select among the interface values instead of indexing a
-          // register array with a runtime index
-          if (t < 0) v[k] -= bd[o + R] * (R + t == 0 ? xi[0] : xi[R - 1]);        // row R+t of x~_i
-          else if (t >= S) v[k] -= bd[o + R] * (t - S == 0 ? xi1[0] : xi1[R - 1]);  // row t-S of x~_{i+1}
+          // select among the interface values (a plain two-way choice here
+          // becomes a runtime-indexed stack array)
+          if (t < 0) v[k] -= bd[o + R] * select_idx(xi, R + t);        // row R+t of x~_i
+          else if (t >= S) v[k] -= bd[o + R] * select_idx(xi1, t - S);  // row t-S of x~_{i+1}
         }
       }
     }
