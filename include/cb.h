@@ -176,8 +176,8 @@ typedef struct {
  * batch, either persistent (a resident grid takes line tiles from a device
  * work queue) or with one workgroup per line tile
  * (a class is r, rows per lane, arithmetic, uniform or general lane layout,
- * interior solve and unit-stride or strided rows, as an item's plan and row
- * stride select them; a batch of plans built alike for one scheme and
+ * interior solve, unit-stride or strided rows and stencil half-width (2 or
+ * 3), as an item's plan, row stride and stencil select them; a batch of plans built alike for one scheme and
  * precision is usually a few classes).  Every plan must have partitions = 1 and be cyclic when a
  * stencil is given; n, axis, grid, stencil, precision and refinement count
  * may differ between items.  Each line goes through the same arithmetic as

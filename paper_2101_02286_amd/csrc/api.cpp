@@ -638,7 +638,10 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     // of one kernel class and workgroup size share a launch; W = threads / L.
     const size_t coef_bytes = uni ? 0 : (size_t)sp.ntypes * sp.block * (fp ? 4 : 8);
     const size_t coef_dbl_if = (coef_bytes + 7) / 8;
-    const int RSs = std::max(6, 2 * p.R);  // stencil halo of +-3 rows
+    // kernels for stencils of half-width 2 (plain solves use the identity)
+    // and 3; exchange regions carry the +-Q halo
+    const int Qi = (!it.stencil || (it.stencil->lo >= -2 && it.stencil->hi <= 2)) ? 2 : 3;
+    const int RSs = std::max(2 * Qi, 2 * p.R);
     int W = 0;
     auto lds_bytes = [&](int RS, bool coef, int64_t pitch) {
       return ((size_t)W * L * 2 * RS + (coef ? coef_dbl_if : 0) + (size_t)W * pitch) * 8;
@@ -652,7 +655,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     // needs more lanes (unit stride) or 16 strided lines would not fit
     int nt = 0;
     if (mode == MODE_X) {
-      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_X);
+      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_X, Qi);
       if (bk) nt = std::min(bk->threads, std::max(512, L));
       if (bk && L <= nt) {
         W = nt / L;
@@ -671,7 +674,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       }
     }
     if (mode == MODE_S) {
-      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_S);
+      bk = find_batch_kernel(p.R, sp.M, fp, uni, ilu, MODE_S, Qi);
       // 512 threads, or 16 lines (8 with FP32 refinement, as in launch_line)
       // where lanes need more
       if (bk) nt = std::min(bk->threads, std::max(512, (fp && p.refine_iters > 0 ? 8 : 16) * L));

@@ -432,7 +432,7 @@ const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu) {
 
 const void *stencil_kernel() { return (const void *)&k_stencil; }
 
-const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode) {
+const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q) {
   int cnt = 0;
   const BatchKernel *t = nullptr;
   switch (M) {
@@ -445,7 +445,8 @@ const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu,
     default: return nullptr;
   }
   for (int i = 0; i < cnt; ++i)
-    if (t[i].R == R && t[i].M == M && t[i].fp32 == fp32 && t[i].uni == uni && t[i].ilu == ilu && t[i].mode == mode)
+    if (t[i].R == R && t[i].M == M && t[i].fp32 == fp32 && t[i].uni == uni && t[i].ilu == ilu && t[i].mode == mode &&
+        t[i].Q == Q)
       return &t[i];
   return nullptr;
 }

@@ -103,13 +103,13 @@ struct BatchItemDev {
 struct BatchKernel {
   int R, M, fp32;
   bool uni, ilu;
-  int mode, threads;  // row mode and workgroup size of the instance
+  int mode, Q, threads;  // row mode, stencil half-width and workgroup size of the instance
   const void *fn;
 };
 static_assert(sizeof(BatchHdr) <= 64, "batch queue header must fit its 64-byte slot");
 
 const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu);
-const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode);
+const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q);
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu);
 const void *stencil_kernel();
 

@@ -280,15 +280,16 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_li
 
 
 // ------------------------------------------------------------------------
-// Persistent batched launch: the grid takes tiles from a device work queue
-// that spans the lines of many (grid, axis, plan) items of uneven sizes, all
-// of one kernel class (r, rows per lane, arithmetic, lane layout, interior
-// solve, unit-stride or strided rows).  Every item runs with the fused stencil (an identity stencil for
-// plain solves) and its own tile shape.  A workgroup leaves when the queue is
-// exhausted; the last one to leave resets the queue so the launch can be
+// Batched launch over the lines of many (grid, axis, plan) items of uneven
+// sizes, all of one kernel class (r, rows per lane, arithmetic, lane layout,
+// interior solve, unit-stride or strided rows, stencil half-width Q).  Every
+// item runs with the fused stencil (an identity stencil for plain solves)
+// and its own tile shape.  One workgroup per tile, or persistent: the grid
+// takes tiles from a device work queue; a workgroup leaves when the queue is
+// exhausted, and the last one to leave resets the queue so the launch can be
 // replayed (e.g. from a captured graph) without a memset.
 // ------------------------------------------------------------------------
-template <int R, int M, typename T, bool UNI, bool ILU, int MODE>
+template <int R, int M, typename T, bool UNI, bool ILU, int MODE, int Q>
 __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
                                                                                const BatchItemDev *items,
                                                                                int per_tile) {
@@ -314,7 +315,7 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_ba
       const int64_t X = it.a.xcds, q = G / X, rem = G % X, j = local % X, s = local / X;
       local = j * q + (j < rem ? j : rem) + s;
     }
-    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, local, smem);
+    line_tile<R, M, T, MODE, Q, UNI, ILU>(it.a, local, smem);
     return;
   }
   for (;;) {
@@ -329,7 +330,7 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_ba
       if (items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
     }
     const BatchItemDev &it = items[lo];
-    line_tile<R, M, T, MODE, 3, UNI, ILU>(it.a, t - it.tile_begin, smem);
+    line_tile<R, M, T, MODE, Q, UNI, ILU>(it.a, t - it.tile_begin, smem);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -343,9 +344,11 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_ba
   }
 }
 
-#define CB_BATCH_INST(R, M, T, UNI, ILU, MODE)                                                 \
-  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, MODE, line_max_threads<R, M, T, MODE, UNI>(),          \
-   (const void *)&k_batched<R, M, T, UNI, ILU, MODE>}
+#define CB_BATCH_INSTQ(R, M, T, UNI, ILU, MODE, Q)                                                \
+  {R, M, sizeof(T) == 8 ? 0 : 1, UNI, ILU, MODE, Q, line_max_threads<R, M, T, MODE, UNI>(),        \
+   (const void *)&k_batched<R, M, T, UNI, ILU, MODE, Q>}
+#define CB_BATCH_INST(R, M, T, UNI, ILU, MODE) \
+  CB_BATCH_INSTQ(R, M, T, UNI, ILU, MODE, 2), CB_BATCH_INSTQ(R, M, T, UNI, ILU, MODE, 3)
 #define CB_BATCH_MODE(R, M, T, UNI, ILU) CB_BATCH_INST(R, M, T, UNI, ILU, MODE_X), CB_BATCH_INST(R, M, T, UNI, ILU, MODE_S)
 #define CB_BATCH_T(R, M, UNI, ILU) CB_BATCH_MODE(R, M, double, UNI, ILU), CB_BATCH_MODE(R, M, float, UNI, ILU)
 #define CB_BATCH_R(M, UNI, ILU) CB_BATCH_T(1, M, UNI, ILU), CB_BATCH_T(2, M, UNI, ILU)
