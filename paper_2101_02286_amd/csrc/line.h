@@ -291,7 +291,7 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_li
 // ------------------------------------------------------------------------
 template <int R, int M, typename T, bool UNI, bool ILU, int MODE, int Q>
 __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_batched(BatchHdr *hdr,
-                                                                               const BatchItemDev *items,
+                                                                               const BatchItemDev *__restrict__ items,
                                                                                int per_tile) {
   extern __shared__ double smem[];
   __shared__ int64_t s_tile;
