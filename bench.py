@@ -22,7 +22,7 @@ import torch
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2101_02286_amd import cb, synth  # noqa: E402
+from paper_2101_02286_amd import cb, schemes, synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_DOF = 16
@@ -70,15 +70,9 @@ def kernel_group(plan, axis):
                                       "elim" if i["interior_elimination_strided"] else "pcr")
 
 
-def tri6():
-    # sixth-order collocated compact derivative: bands [1/3, 1, 1/3],
-    # RHS a (f_{j+1}-f_{j-1})/(2h) + b (f_{j+2}-f_{j-2})/(4h), a = 14/9, b = 1/9
-    return [1 / 3, 1.0, 1 / 3], (14 / 9, 1 / 9)
-
-
-def deriv_stencil(n, a, b):
-    h = 2 * math.pi / n
-    return cb.Stencil(-2, [-b / (4 * h), -a / (2 * h), 0.0, a / (2 * h), b / (4 * h)])
+def scheme_stencil(name, n):
+    """cb.Stencil of a named compact scheme's right-hand side for lines of n points."""
+    return cb.Stencil(*schemes.stencil(name, n))
 
 
 def cpu_baseline(f_dev, bands, stencils, seconds=10.0):
@@ -111,8 +105,8 @@ def headline(args):
     dev = torch.device("cuda:0")
     n = args.n
     shape = (n, n, n)
-    bands, (a, b) = tri6()
-    st = deriv_stencil(n, a, b)
+    bands = schemes.bands("tri6")
+    st = scheme_stencil("tri6", n)
     f, _ = synth.random_modes(shape, seed=0, device=dev)
     if not args.tune:  # the plans' automatic launch shape
         plans = [cb.Plan(bands, n)] * 3
@@ -204,10 +198,10 @@ def mode_two_level(args):
     """n = 8192 lines (64 x 64 of them) split into P = 16 workgroup partitions."""
     dev = torch.device("cuda:0")
     n, P = 8192, 16
-    bands, (a, b) = tri6()
+    bands = schemes.bands("tri6")
     plan = cb.Plan(bands, n, partitions=P)
     f, _ = synth.random_modes((64, 64, n), seed=3, device=dev)
-    rhs = cb.rhs_stencil(deriv_stencil(n, a, b), f, 0)
+    rhs = cb.rhs_stencil(scheme_stencil("tri6", n), f, 0)
     x = torch.empty_like(rhs)
     stream = torch.cuda.current_stream()
     dur, wall = _time_launches(lambda: cb.solve(plan, rhs, 0, out=x, stream=stream), args.steps, args.warmup, stream)
@@ -225,10 +219,8 @@ def mode_penta_z(args):
     """512^3 tenth-order pentadiagonal compact derivative along z."""
     dev = torch.device("cuda:0")
     n = args.n
-    a, b, c = 17 / 12, 101 / 150, 1 / 100
-    bands = [1 / 20, 1 / 2, 1.0, 1 / 2, 1 / 20]
-    h = 2 * math.pi / n
-    st = cb.Stencil(-3, [-c / (6 * h), -b / (4 * h), -a / (2 * h), 0.0, a / (2 * h), b / (4 * h), c / (6 * h)])
+    bands = schemes.bands("penta10")
+    st = scheme_stencil("penta10", n)
     plan = cb.Plan(bands, n)
     f, _ = synth.random_modes((n, n, n), seed=1, device=dev)
     out = torch.empty_like(f)
@@ -249,7 +241,7 @@ def mode_batched(args):
     tile; the persistent work-queue form is timed beside it): FP32+refinement vs FP64."""
     dev = torch.device("cuda:0")
     shapes = synth.grid_batch_shapes(seed=0, count=12)
-    bands, (a, b) = tri6()
+    bands = schemes.bands("tri6")
     fields = []
     for gi, (nx, ny, nz) in enumerate(shapes):
         f, _ = synth.random_modes((nz, ny, nx), seed=gi, device=dev)
@@ -267,7 +259,7 @@ def mode_batched(args):
                 # ...) per grid shape and axis; else one default plan per n
                 key_p = (n, tuple(f.shape), ax) if args.tune else n
                 if key_p not in plans:
-                    st = deriv_stencil(n, a, b)
+                    st = scheme_stencil("tri6", n)
                     if args.tune:
                         from paper_2101_02286_amd import tune
                         best, _ = tune.tune(bands, n, f, ax, stencil=st, precision=prec, refine_iters=iters,
@@ -336,9 +328,8 @@ def mode_serve(args):
     def run(rate, precision, count=args.requests):
         reqs = poisson_requests(count, rate_hz=rate, seed=11, max_points=args.max_points)
         ex = GpuExecutor(slots=8, precision=precision)
-        for r in reqs:  # factorise every plan before the clock starts
-            ex.plan(r.scheme, r.n)
-        srv = Server(ex, hbm_budget=args.budget_gb * (1 << 30), slots=8, max_batch=4)
+        ex.stage(reqs)  # inputs resident in HBM and plans factorised before the clock starts
+        srv = Server(ex, hbm_budget=args.budget_gb * (1 << 30) if args.budget_gb else None, slots=8, max_batch=4)
         st = srv.run(reqs)
         st["rate_hz"] = rate
         st["precision"] = precision
@@ -377,7 +368,8 @@ def main():
                     help="batched launches: < 0 one workgroup per tile (default); 0 persistent queue with all "
                          "workgroups that fit; > 0 persistent queue with at most that many")
     ap.add_argument("--max-points", type=float, default=1.5e8)
-    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="serving admission budget; 0 = a share of the device's free memory")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

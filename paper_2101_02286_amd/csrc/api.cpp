@@ -266,6 +266,17 @@ int tile_xcds(const Plan &p, int mode, int W, int64_t rs) {
   return on ? xcd_count() : 1;
 }
 
+// Bands of the FP64 refinement residual b - A x.  Constant cyclic bands are
+// the same on every row and go by value; per-row bands, and acyclic plans
+// (whose first and last r rows lose the entries that fall outside the
+// matrix), are read per row from the plan's expanded [n][2r+1] table.
+void residual_bands(const Plan &p, LineArgs &a) {
+  const int W = 2 * p.R + 1;
+  const size_t mid = (size_t)(p.n / 2) * W;  // an interior row: every entry present
+  for (int o = 0; o < W; ++o) a.bands[o] = p.bands[mid + o];
+  a.bands_row = (p.desc.per_row || !p.desc.cyclic) ? p.d_bands : nullptr;
+}
+
 // --------------------------------------------------------- P = 1 launch --
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                       hipStream_t stream) {
@@ -359,8 +370,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   a.stage_pitch = pitch;
   a.seg = p.segdev_host[si];
   if (st) stencil_q(st, a.stc);
-  for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
-  a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
+  residual_bands(p, a);
   const size_t lds = lds_of(W);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
@@ -718,8 +728,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.seg = p.segdev_host[si];
     if (it.stencil) stencil_q(it.stencil, a.stc);
     else a.stc[3] = 1.0;  // identity stencil: b = input
-    for (int o = 0; o < 2 * p.R + 1; ++o) a.bands[o] = p.bands[o];
-    a.bands_row = p.desc.per_row ? p.d_bands : nullptr;
+    residual_bands(p, a);
     d.mode = mode;
     ntiles[i] = (g.nlines + W - 1) / W;
     int c = 0;

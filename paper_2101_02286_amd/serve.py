@@ -12,12 +12,20 @@ free up.  Latency = completion - arrival.
 The scheduling policy (`Server`) is independent of the device: it drives an
 executor with four calls (alloc, launch, done, release).  `GpuExecutor` runs
 the HIP library; tests drive the policy with a fake executor and clock.
+
+Request inputs are staged on the device before the served clock starts
+(`GpuExecutor.stage`, standing in for data that a client has already placed
+in HBM); admission then accounts for each request's input and output bytes
+against a budget taken from the device's free memory (hipMemGetInfo) unless
+one is given.
 """
 import collections
 import math
 import time
 
 import numpy as np
+
+from . import schemes
 
 
 class Request:
@@ -44,9 +52,10 @@ class Request:
 class Server:
     # defaults: 8 slots and batches of at most 4 requests balanced the slots
     # best on a saturated stream of random-size requests (MI355X)
-    def __init__(self, executor, hbm_budget, slots=8, max_batch=4, clock=time.perf_counter):
+    def __init__(self, executor, hbm_budget=None, slots=8, max_batch=4, clock=time.perf_counter):
         self.ex = executor
-        self.budget = int(hbm_budget)
+        # no budget given: what the executor reports as free device memory
+        self.budget = int(hbm_budget if hbm_budget is not None else executor.budget_bytes())
         self.slots = slots
         self.max_batch = max_batch
         self.clock = clock
@@ -58,6 +67,7 @@ class Server:
         self.finished = []
         self.peak_used = 0
         self.max_inflight = 0
+        self.batch_sizes = []                # requests per launched batch
 
     def submit(self, req):
         if req.mem > self.budget:
@@ -102,6 +112,7 @@ class Server:
             for r in reqs:
                 r.launch_t = t
             h = self.ex.launch(slot, reqs)
+            self.batch_sizes.append(len(reqs))
             self.inflight.append((slot, h, reqs))
             self.max_inflight = max(self.max_inflight, len(self.inflight))
 
@@ -138,7 +149,8 @@ class Server:
         return {"requests": len(self.finished), "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
                 "gdofs": dof / span / 1e9, "span_s": span, "peak_bytes": self.peak_used,
-                "max_inflight_batches": self.max_inflight}
+                "budget_bytes": self.budget, "max_inflight_batches": self.max_inflight,
+                "batches": len(self.batch_sizes), "max_batch_requests": max(self.batch_sizes, default=0)}
 
 
 def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_points=1.5e8,
@@ -163,6 +175,9 @@ def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_point
 class GpuExecutor:
     """Runs request groups as one batched launch per stream slot."""
 
+    # share of the device's free memory that admission may hand to requests
+    BUDGET_FRACTION = 0.8
+
     def __init__(self, slots=8, precision="fp32_refine", refine_iters=0, rows_per_lane=0, device="cuda:0",
                  on_result=None):
         import torch
@@ -175,20 +190,14 @@ class GpuExecutor:
         self.ws = {}
         self.plans = {}
         self.stencils = {}
+        self.inputs = {}
 
     def plan(self, scheme, n):
         key = (scheme, n)
         if key not in self.plans:
-            a, b, c, al, be = _scheme(scheme)
-            bands = [be, al, 1.0, al, be] if be else [al, 1.0, al]
-            self.plans[key] = self.cb.Plan(bands, n, precision=self.precision, refine_iters=self.refine_iters,
-                                           rows_per_lane=self.rpl)
-            h = 2 * math.pi / n
-            if c:
-                st = [-c / (6 * h), -b / (4 * h), -a / (2 * h), 0.0, a / (2 * h), b / (4 * h), c / (6 * h)]
-                self.stencils[key] = self.cb.Stencil(-3, st)
-            else:
-                self.stencils[key] = self.cb.Stencil(-2, [-b / (4 * h), -a / (2 * h), 0.0, a / (2 * h), b / (4 * h)])
+            self.plans[key] = self.cb.Plan(schemes.bands(scheme), n, precision=self.precision,
+                                           refine_iters=self.refine_iters, rows_per_lane=self.rpl)
+            self.stencils[key] = self.cb.Stencil(*schemes.stencil(scheme, n))
         return self.plans[key], self.stencils[key]
 
     def group_key(self, r):
@@ -196,13 +205,29 @@ class GpuExecutor:
         # kernel class), so every request may join every batch
         return 0
 
-    def alloc(self, r):
+    def stage(self, requests):
+        """Place every request's input in HBM (seeded U(0, 1) fields) and
+        factorise its plan, before the served clock starts."""
         torch = self.torch
-        nx, ny, nz = r.shape
-        g = torch.Generator(device=self.device)
-        g.manual_seed(r.seed)
-        f = torch.rand((nz, ny, nx), generator=g, device=self.device, dtype=torch.float64)
-        r.bufs = (f, torch.empty_like(f))
+        for r in requests:
+            self.plan(r.scheme, r.n)
+            if r.rid not in self.inputs:
+                nx, ny, nz = r.shape
+                g = torch.Generator(device=self.device)
+                g.manual_seed(r.seed)
+                self.inputs[r.rid] = torch.rand((nz, ny, nx), generator=g, device=self.device, dtype=torch.float64)
+        torch.cuda.synchronize(self.device)
+
+    def budget_bytes(self):
+        """Admission budget: a share of the device memory free now (hipMemGetInfo)."""
+        free, _total = self.torch.cuda.mem_get_info(self.device)
+        return int(free * self.BUDGET_FRACTION)
+
+    def alloc(self, r):
+        f = self.inputs.get(r.rid)
+        if f is None:
+            raise KeyError("request %d was not staged" % r.rid)
+        r.bufs = (f, self.torch.empty_like(f))
 
     def launch(self, slot, reqs):
         torch, cb = self.torch, self.cb
@@ -241,11 +266,5 @@ class GpuExecutor:
         if self.on_result is not None:
             self.on_result(r, r.bufs[0], r.bufs[1])
         r.bufs = None
+        self.inputs.pop(r.rid, None)
 
-
-def _scheme(name):
-    if name == "tri6":
-        return 14 / 9, 1 / 9, 0.0, 1 / 3, 0.0
-    if name == "penta10":
-        return 17 / 12, 101 / 150, 1 / 100, 1 / 2, 1 / 20
-    raise ValueError(name)

@@ -2,7 +2,8 @@
 
 Tolerances: FP64 and FP32+refinement results must match the oracle to a
 relative max error of 1e-12 (max |x - x_ref| / max |x_ref|); plain FP32 to
-1e-6 for tridiagonal systems (measured and reported for pentadiagonal).
+1e-6 where the matrix's condition number allows it (tridiagonal schemes),
+else to 2 kappa 2^-24 (fp32_bound).
 """
 import math
 
@@ -84,13 +85,28 @@ def test_fused_operators(gpu, scheme, axis, n):
 @pytest.mark.parametrize("n", [5, 8, 32, 37, 128, 512, 613, 1024])
 def test_solve_random_rhs(gpu, bands, axis, n):
     bd = TRI if bands == "tri" else PENTA
-    if n < 2 * len(bd) // 2 + 1:
+    if n < len(bd):  # a cyclic system needs n >= 2r + 1 rows
         pytest.skip("n too small")
     shape = shape_with(axis, n, other=(9, 7))
     b = synth.random_uniform(shape, seed=n * 3 + axis)
     plan = cb.Plan(bd, n)
     x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
     ref = oracle.solve_axis(b.numpy(), axis, bd)
+    assert relerr(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("bands,n", [(TRI, 512), (TRI, 613), (PENTA, 200), (PENTA, 512), (TRI, 5), (PENTA, 9)])
+def test_solve_acyclic_constant_bands(gpu, axis, prec, bands, n):
+    """Acyclic systems with the same bands on every row (the first and last r
+    rows lose the entries outside the matrix), FP64 and FP32 + refinement,
+    whose FP64 residual must use those truncated end rows."""
+    shape = shape_with(axis, n, other=(9, 7))
+    b = synth.random_uniform(shape, seed=n + 5 * axis)
+    plan = cb.Plan(bands, n, cyclic=False, precision=prec)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, bands, cyclic=False)
     assert relerr(x, ref) <= 1e-12
 
 
@@ -174,7 +190,22 @@ def test_fp32_and_refinement(gpu, bands, axis):
     er = relerr(cb.apply_derivative(pr, st, f.to(gpu), axis).cpu().numpy(), ref)
     print("fp32 %s: plain %.2e refined %.2e" % (bands, e32, er))
     assert er <= 1e-12
-    assert e32 <= (1e-6 if bands == "tri" else 5e-6)
+    assert e32 <= fp32_bound(bd)
+
+
+def fp32_bound(bands):
+    """Error bound of a plain FP32 solve: 1e-6, the target, when the matrix
+    allows it; else 2 kappa u, kappa the ratio of the extreme values of the
+    band symbol a0 + 2 sum a_j cos(j t) (the cyclic matrix's condition number)
+    and u = 2^-24.  Rounding the right-hand side to FP32 alone perturbs it by
+    u, which the solve amplifies by up to kappa: the tenth-order pentadiagonal
+    matrix has kappa = 2.1 / 0.1 = 21, so about 1.3e-6 is reachable there and
+    no FP32 solve can promise 1e-6 (FP32 + refinement does, at 1e-12)."""
+    r = (len(bands) - 1) // 2
+    t = np.linspace(0.0, np.pi, 4097)
+    f = bands[r] + sum(2 * bands[r + j] * np.cos(j * t) for j in range(1, r + 1))
+    kappa = np.abs(f).max() / np.abs(f).min()
+    return max(1e-6, 2 * kappa * 2.0 ** -24)
 
 
 def test_refinement_ragged_solve(gpu):
@@ -212,59 +243,63 @@ def test_errors_leave_output_untouched(gpu):
         cb.solve(host, b, 0, out=out)
 
 
-# ------------------------------------------------ full sizes, sampled lines --
-def sample_lines(arr, axis, picks):
-    """Lines (k, n) of a (nz, ny, nx) array along `axis` at (u, v) picks."""
-    if axis == 0:
-        return np.stack([arr[v, u, :] for u, v in picks])
-    if axis == 1:
-        return np.stack([arr[v, :, u] for u, v in picks])
-    return np.stack([arr[:, v, u] for u, v in picks])
+# --------------------------------------------- full sizes, every line ----
+def full_check(f_dev, out_dev, axis, bands, lo, c):
+    """Relative max error of a whole GPU output against the oracle's fused
+    derivative of the whole grid (every line compared element by element)."""
+    torch.cuda.synchronize()
+    ref = oracle.apply_axis(f_dev.cpu().numpy(), axis, bands, lo, c)
+    return relerr(out_dev.cpu().numpy(), ref)
 
 
-def sampled_check(f, out, axis, bands, lo, c, count=48, seed=0):
-    nz, ny, nx = f.shape
-    du, dv = [(ny, nz), (nx, nz), (nx, ny)][axis]
-    rng = np.random.default_rng(seed)
-    picks = [(int(rng.integers(du)), int(rng.integers(dv))) for _ in range(count)]
-    picks += [(0, 0), (du - 1, dv - 1)]  # first and last line
-    fl = sample_lines(f, axis, picks)[None]  # (1, k, n): lines along x
-    ref = oracle.apply_axis(fl, 0, bands, lo, c)[0]
-    got = sample_lines(out, axis, picks)
-    return relerr(got, ref)
+def nan_like(t):
+    """An output buffer prefilled with NaN, so an unwritten element fails."""
+    return torch.full_like(t, float("nan"))
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_headline_512_full_size_sampled(gpu, axis):
-    """The benchmark's launch configuration on the full 512^3 grid."""
+def test_headline_512_full_size(gpu, axis):
+    """The benchmark's launch configuration on the full 512^3 grid, every line."""
     n = 512
     f, _ = synth.random_modes((n, n, n), seed=0, device=gpu)
     lo, c = deriv_stencil(schemes.DERIV6, n)
-    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis)
-    torch.cuda.synchronize()
-    assert sampled_check(f.cpu().numpy(), out.cpu().numpy(), axis, TRI, lo, c) <= 1e-12
+    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis, out=nan_like(f))
+    assert full_check(f, out, axis, TRI, lo, c) <= 1e-12
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_c2_256_full_size_sampled(gpu, axis):
+def test_c2_256_full_size(gpu, axis):
+    """256^3: sixth-order derivative and collocated -> staggered interpolation."""
     n = 256
     f, _ = synth.random_modes((n, n, n), seed=2, device=gpu)
-    fh = f.cpu().numpy()
     lo, c = deriv_stencil(schemes.DERIV6, n)
-    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis).cpu().numpy()
-    assert sampled_check(fh, out, axis, TRI, lo, c) <= 1e-12
+    out = cb.apply_derivative(cb.Plan(TRI, n), cb.Stencil(lo, c), f, axis, out=nan_like(f))
+    assert full_check(f, out, axis, TRI, lo, c) <= 1e-12
     lo, c = schemes.stencil_interp_c2s(schemes.INTERP6)
-    out = cb.apply_derivative(cb.Plan(INTERP, n), cb.Stencil(lo, c), f, axis).cpu().numpy()
-    assert sampled_check(fh, out, axis, INTERP, lo, c) <= 1e-12
+    out = cb.apply_derivative(cb.Plan(INTERP, n), cb.Stencil(lo, c), f, axis, out=nan_like(f))
+    assert full_check(f, out, axis, INTERP, lo, c) <= 1e-12
 
 
-def test_c3b_512_penta_z_full_size_sampled(gpu):
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_c3b_512_penta_full_size(gpu, axis):
+    """512^3 tenth-order pentadiagonal derivative (z is the configuration's
+    axis; x and y are what the benchmark times beside it)."""
     n = 512
     f, _ = synth.random_modes((n, n, n), seed=1, device=gpu)
     lo, c = deriv_stencil(schemes.DERIV10, n)
-    out = cb.apply_derivative(cb.Plan(PENTA, n), cb.Stencil(lo, c), f, 2)
+    out = cb.apply_derivative(cb.Plan(PENTA, n), cb.Stencil(lo, c), f, axis, out=nan_like(f))
+    assert full_check(f, out, axis, PENTA, lo, c) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_headline_512_plain_solve_full_size(gpu, axis):
+    """cb_solve on a 512^3 right-hand side (the benchmark's plain-solve lines)."""
+    n = 512
+    b = synth.random_uniform((n, n, n), seed=axis, device=gpu)
+    x = cb.solve(cb.Plan(TRI, n), b, axis, out=nan_like(b))
     torch.cuda.synchronize()
-    assert sampled_check(f.cpu().numpy(), out.cpu().numpy(), 2, PENTA, lo, c) <= 1e-12
+    ref = oracle.solve_axis(b.cpu().numpy(), axis, TRI)
+    assert relerr(x.cpu().numpy(), ref) <= 1e-12
 
 
 @pytest.mark.parametrize("P", [4, 7])

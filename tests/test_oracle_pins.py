@@ -363,3 +363,102 @@ def test_pins_catch_planted_mistakes(mi, tmp_path, monkeypatch):
         except (AssertionError, oracle.OracleError):
             failed += 1
     assert failed >= 1, "planted mistake %d went unnoticed" % mi
+
+
+# ------------------------------------- staggered -> collocated (App. A.2) ---
+def _staggered_mode(n, kk, phi):
+    """A cosine sampled on the staggered points x_{m+1/2} (entry m), and the grid."""
+    h = 2 * np.pi / n
+    x = np.arange(n) * h
+    return np.cos(kk * (x + h / 2) + phi)[None, None, :], x, h
+
+
+def test_interpolation_staggered_to_collocated_closed_form(sch=schemes):
+    """Staggered -> collocated interpolation: entry m of the input sits at
+    x_{m+1/2}; the result at x_j equals T(kh) cos(k x_j + phi) with the same
+    transfer function T(kh) = [a cos(kh/2) + b cos(3kh/2)] / [1 + 2 alpha cos kh]
+    as the collocated -> staggered direction (App. A.2)."""
+    s = sch.INTERP6
+    n = 40
+    lo, c = sch.stencil_interp_s2c(s)
+    bands = [float(s["alpha"]), 1.0, float(s["alpha"])]
+    for kk in (1, 4, 9, 13):
+        f, x, h = _staggered_mode(n, kk, 0.7)
+        out = oracle.apply_axis(f, 0, bands, lo, c)[0, 0]
+        kh = kk * h
+        T = (float(s["a"]) * np.cos(kh / 2) + float(s["b"]) * np.cos(1.5 * kh)) / (
+            1 + 2 * float(s["alpha"]) * np.cos(kh))
+        assert np.abs(out - T * np.cos(kk * x + 0.7)).max() <= 1e-13, kk
+
+
+def test_staggered_derivative_to_collocated_closed_form(sch=schemes):
+    """Staggered derivative read from staggered points onto the collocated
+    grid: f'_j = -k' sin(k x_j + phi) with the App. A.2 modified wavenumber
+    k' h = [2a sin(kh/2) + (2b/3) sin(3kh/2)] / [1 + 2 alpha cos kh]."""
+    s = sch.STAG6
+    n = 44
+    bands = [float(s["alpha"]), 1.0, float(s["alpha"])]
+    for kk in (1, 6, 15):
+        f, x, h = _staggered_mode(n, kk, -0.4)
+        lo, c = sch.stencil_deriv_s2c(s, h)
+        d = oracle.apply_axis(f, 0, bands, lo, c)[0, 0]
+        kh = kk * h
+        kp = (2 * float(s["a"]) * np.sin(kh / 2) + 2 * float(s["b"]) / 3 * np.sin(1.5 * kh)) / (
+            1 + 2 * float(s["alpha"]) * np.cos(kh)) / h
+        ref = -kp * np.sin(kk * x - 0.4)
+        # rounding grows with n (the 1/h weights cancel): 4 n eps relative
+        assert np.abs(d - ref).max() <= 4 * n * np.finfo(float).eps * np.abs(ref).max(), kk
+
+
+def test_staggered_round_trip_converges():
+    """Collocated -> staggered -> collocated interpolation of a smooth mode
+    returns it to sixth order in h (errors of both directions multiply T^2)."""
+    s = schemes.INTERP6
+    bands = [float(s["alpha"]), 1.0, float(s["alpha"])]
+    errs = []
+    for n in (16, 32):
+        x = np.arange(n) * 2 * np.pi / n
+        f = np.cos(2 * x + 0.1)[None, None, :]
+        lo, c = schemes.stencil_interp_c2s(s)
+        half = oracle.apply_axis(f, 0, bands, lo, c)
+        lo, c = schemes.stencil_interp_s2c(s)
+        back = oracle.apply_axis(half, 0, bands, lo, c)[0, 0]
+        errs.append(np.abs(back - f[0, 0]).max())
+    rate = math.log2(errs[0] / errs[1])
+    assert 5.5 < rate < 7.5, rate
+
+
+SCHEME_MUTATIONS = [
+    # staggered -> collocated interpolation shifted by one point (off-by-one lo)
+    ('    return -2, [b / 2, a / 2, a / 2, b / 2]', '    return -1, [b / 2, a / 2, a / 2, b / 2]'),
+    # staggered -> collocated derivative with its inner weights' signs swapped
+    ('    return -2, [-b / (3 * h), -a / h, a / h, b / (3 * h)]',
+     '    return -2, [-b / (3 * h), a / h, -a / h, b / (3 * h)]'),
+    # staggered -> collocated derivative with inner and outer weights exchanged
+    ('    return -2, [-b / (3 * h), -a / h, a / h, b / (3 * h)]',
+     '    return -2, [-a / h, -b / (3 * h), b / (3 * h), a / h]'),
+    # staggered -> collocated interpolation with the outer weight halved twice
+    ('    return -2, [b / 2, a / 2, a / 2, b / 2]', '    return -2, [b / 4, a / 2, a / 2, b / 4]'),
+]
+
+
+@pytest.mark.parametrize("mi", range(len(SCHEME_MUTATIONS)))
+def test_scheme_pins_catch_planted_mistakes(mi):
+    """Plant one mistake in a private copy of the oracle's scheme builders and
+    check that the staggered -> collocated closed-form pins reject it."""
+    import os
+    import types
+
+    src = open(os.path.join(os.path.dirname(schemes.__file__), "schemes.py")).read()
+    old, new = SCHEME_MUTATIONS[mi]
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("mutated_schemes")
+    exec(compile(src.replace(old, new), "mutated_schemes", "exec"), mod.__dict__)
+    failed = 0
+    for chk in (test_interpolation_staggered_to_collocated_closed_form,
+                test_staggered_derivative_to_collocated_closed_form):
+        try:
+            chk(sch=mod)
+        except AssertionError:
+            failed += 1
+    assert failed >= 1, "planted mistake %d went unnoticed" % mi
