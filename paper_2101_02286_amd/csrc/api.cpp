@@ -252,7 +252,7 @@ cb_status check_stencil(const cb_stencil *st) {
 }
 
 cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
-                    hipStream_t stream);
+                    hipStream_t stream, const FixedScratch *fs);
 
 // Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
 // turn, so in launch order neighbouring tiles run on different XCDs):
@@ -279,9 +279,9 @@ void residual_bands(const Plan &p, LineArgs &a) {
 
 // --------------------------------------------------------- P = 1 launch --
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
-                      hipStream_t stream) {
+                      hipStream_t stream, const FixedScratch *fs) {
   // long strided lines: workgroup partitions of the same matrix
-  if (g.rs != 1 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream);
+  if (g.rs != 1 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
   const int si = g.rs == 1 ? 0 : p.seg_s;  // lane layout for this launch's row stride
   const SegPlan &sp = p.segs[si];
   const bool uni = sp.uniform != 0;
@@ -305,6 +305,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (!lk) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
   const void *fn = lk->fn;
   const int L = sp.L;
+  if (L > 1024 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
   if (L > 1024) return fail(CB_ERR_UNSUPPORTED, "line needs more than 1024 lanes");
   int W;
   if (p.desc.lines_per_wg > 0) {
@@ -340,8 +341,12 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const size_t cap = lds_cap();
   while (W > 1 && (lds_of(W) > cap || W * L > lk->max_threads)) W /= 2;
   const int NT = W * L;
-  if (lds_of(W) > cap || NT > lk->max_threads)
+  if (lds_of(W) > cap || NT > lk->max_threads) {
+    // a line longer than one workgroup of this kernel holds: the workgroup
+    // partitions of the same matrix when the plan has them (FP64, n > 4096)
+    if (p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
     return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup of this kernel");
+  }
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
   // one wavefront and its exchanges need no workgroup barrier
   const bool wave_local = mode == MODE_X && L <= 64 && (64 % L == 0) && p.desc.block_barriers == 0;
@@ -382,8 +387,11 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
 }
 
 // --------------------------------------------------------- P > 1 launch --
+// The 3r values per (line, partition) that phases A-C share live in a
+// stream-ordered allocation of the launch, or in the caller's fixed buffer
+// `fs` (checked against its size before anything is enqueued).
 cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
-                    hipStream_t stream) {
+                    hipStream_t stream, const FixedScratch *fs) {
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
   const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;  // stencil half-width of the kernel
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
@@ -449,10 +457,19 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.mats = p.d_mats;
   const size_t sbytes = (size_t)g.nlines * p.P * 3 * p.R * sizeof(double);
   void *scratch = nullptr;
-  hipError_t e = hipMallocAsync(&scratch, std::max<size_t>(sbytes, 256), stream);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
+  hipError_t e = hipSuccess;
+  if (fs) {
+    if (sbytes > fs->bytes)
+      return fail(CB_ERR_UNSUPPORTED, "this solve needs " + std::to_string(sbytes) +
+                                          " bytes of partition scratch, more than the " + std::to_string(fs->bytes) +
+                                          " bytes of the fixed buffer");
+    scratch = fs->ptr;
+  } else {
+    e = hipMallocAsync(&scratch, std::max<size_t>(sbytes, 256), stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
+    }
   }
   a.scratch = static_cast<double *>(scratch);
   const int64_t tiles = (g.nlines + W - 1) / W;
@@ -464,7 +481,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   if (e == hipSuccess)
     e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
-  hipError_t e2 = hipFreeAsync(scratch, stream);
+  const hipError_t e2 = fs ? hipSuccess : hipFreeAsync(scratch, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
   return CB_OK;
@@ -478,6 +495,28 @@ cb_status check_plan_for_solve(cb_plan_t plan) {
 }
 
 }  // namespace
+
+// x = A^{-1} b along one axis: cb_solve (fs == NULL: partitioned lines take
+// a stream-ordered scratch allocation) and the allocation-free variant (fs:
+// the caller's fixed buffer).
+cb_status solve_entry(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b, double *x, void *stream,
+                      const FixedScratch *fs) {
+  cb_status s = check_plan_for_solve(plan);
+  if (s) return s;
+  Geo g;
+  if ((s = geometry(grid, axis, g))) return s;
+  if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
+    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
+  if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
+  if (!b || !x) return fail(CB_ERR_INVALID_ARG, "b and x must be non-NULL");
+  if (b != x && overlap(b, x, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "b and x overlap");
+  if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream), fs);
+  return launch_wg(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream), fs);
+}
+
+cb_status set_error(cb_status s, const char *msg) { return fail(s, msg); }
+
 }  // namespace cb
 
 using namespace cb;
@@ -561,20 +600,7 @@ cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t
 
 cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b, double *x,
                    void *stream) {
-  cb_status s = check_plan_for_solve(plan);
-  if (s) return s;
-  Geo g;
-  if ((s = geometry(grid, axis, g))) return s;
-  if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
-  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
-    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
-  if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
-  if (!b || !x) return fail(CB_ERR_INVALID_ARG, "b and x must be non-NULL");
-  if (b != x && overlap(b, x, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "b and x overlap");
-  if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
-  if (plan->p.precision != CB_FP64)
-    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
-  return launch_wg(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream));
+  return solve_entry(plan, grid, axis, b, x, stream, nullptr);
 }
 
 cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid, int32_t axis,
@@ -592,9 +618,9 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
   if (!f || !out) return fail(CB_ERR_INVALID_ARG, "f and out must be non-NULL");
   if (overlap(f, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and out overlap");
   if (plan->p.P != 1) {
-    return launch_wg(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
+    return launch_wg(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream), nullptr);
   }
-  return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream));
+  return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream), nullptr);
 }
 
 size_t cb_batch_workspace_size(int32_t n_items) {

@@ -1,5 +1,6 @@
 // Kernel argument blocks and dispatch tables shared by kernels.hip and api.cpp.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 #include "plan.h"
@@ -107,6 +108,20 @@ struct BatchKernel {
   const void *fn;
 };
 static_assert(sizeof(BatchHdr) <= 64, "batch queue header must fit its 64-byte slot");
+
+// A caller-owned device buffer that P > 1 launches use for their partition
+// scratch instead of allocating one.
+struct FixedScratch {
+  void *ptr;
+  size_t bytes;
+};
+
+// cb_solve with the partition scratch in `fs` (NULL: a stream-ordered
+// allocation per launch), and the error reporting of the C ABI
+// (cb_last_error's message).
+cb_status solve_entry(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b, double *x, void *stream,
+                      const FixedScratch *fs);
+cb_status set_error(cb_status s, const char *msg);
 
 const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu);
 const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q);

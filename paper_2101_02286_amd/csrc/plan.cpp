@@ -569,12 +569,14 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
       }
   }
   // general layout (lanes of two sizes): unit-stride launches prefer 8 rows
-  // per lane, strided ones 16 (fewer lanes, so 16 lines share a workgroup)
+  // per lane while a line needs at most 512 of them (the thread bound of the
+  // general unit-stride kernels), strided ones 16 (fewer lanes, so 16 lines
+  // share a workgroup)
   uniform = false;
   m_uni = 0;
   if (M_req) M = M_req;
   else if (pref == PREF_S) M = m_max >= 16 ? 16 : 8;
-  else M = ((S + 7) / 8 <= 1024 || m_max < 16) ? 8 : 16;
+  else M = ((S + 7) / 8 <= 512 || m_max < 16) ? 8 : 16;
   if (M != 8 && M != 16) return false;
   if (L_req > 0) {
     L = L_req;

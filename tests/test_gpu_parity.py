@@ -160,6 +160,38 @@ def test_partitioned_lines(gpu, P, bands, axis, xs):
     assert relerr(x, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("P", [3, 4])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_partitioned_acyclic_lines(gpu, P, bands, axis):
+    """Acyclic systems split over P workgroup partitions: the first partition
+    has no coupling to the last one (no corner blocks)."""
+    bd = TRI if bands == "tri" else PENTA
+    n = 80 * P + 3
+    shape = shape_with(axis, n, other=(6, 5))
+    b = synth.random_uniform(shape, seed=10 + P + axis)
+    plan = cb.Plan(bd, n, partitions=P, cyclic=False)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, bd, cyclic=False)
+    assert relerr(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [4100, 6000, 10000])
+def test_long_ragged_unit_stride_lines(gpu, n):
+    """Ragged unit-stride lines longer than 4096 rows: 16-row lanes in one
+    workgroup while 512 lanes suffice, else the plan's workgroup partitions
+    (solve and fused derivative)."""
+    shape = (3, 2, n)
+    b = synth.random_uniform(shape, seed=n)
+    plan = cb.Plan(TRI, n)
+    x = cb.solve(plan, b.to(gpu), 0).cpu().numpy()
+    assert relerr(x, oracle.solve_axis(b.numpy(), 0, TRI)) <= 1e-12
+    f, _ = synth.random_modes(shape, seed=n)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), 0).cpu().numpy()
+    assert relerr(out, oracle.apply_axis(f.numpy(), 0, TRI, lo, c)) <= 1e-12
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192
