@@ -36,6 +36,7 @@
 #ifndef CB_H
 #define CB_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -159,6 +160,25 @@ cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const doub
  * memory).  Requires a cyclic plan.  f and out must not overlap. */
 cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid,
                               int32_t axis, const double *f, double *out, void *stream);
+
+/* cb_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, checks and results (bitwise) as cb_solve, which takes a
+ * stream-ordered allocation for the partition scratch of lines split over
+ * P > 1 workgroups (also strided launches of FP64 one-partition plans with
+ * n > 4096): 3r doubles per line and partition.  This variant uses instead a
+ * fixed array of CB_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
+ * held until the process ends, and never calls hipMalloc, hipFree or any
+ * other allocating routine.  A solve that would need more scratch (lines x
+ * partitions x 3r x 8 bytes above the limit, e.g. more than 1,398,101
+ * tridiagonal line-partitions) returns CB_ERR_UNSUPPORTED before anything is
+ * enqueued.  The first call on a device resolves the array's address there
+ * (make that call outside graph capture).  Every call on one GPU shares its
+ * array, so calls that overlap in time on one GPU (other streams, other
+ * threads) race; calls in one stream's order do not. */
+#define CB_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+cb_status cb_solve_noalloc(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b,
+                           double *x, void *stream);
 
 /* One work item of a batched launch: a solve (stencil == NULL) or a fused
  * derivative along one axis of one grid. */

@@ -16,6 +16,7 @@ _lib = None
 CB_OK, CB_ERR_INVALID_ARG, CB_ERR_UNSUPPORTED, CB_ERR_SINGULAR, CB_ERR_OOM, CB_ERR_HIP = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
 ABI_SYMBOLS = ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
+               "cb_solve_noalloc",
                "cb_batch_workspace_size", "cb_batch_build", "cb_batch_launch", "cb_solve_batched",
                "cb_plan_get_info",
                "cb_plan_get_schedule", "cb_plan_get_array", "cb_last_error")
@@ -75,6 +76,7 @@ def lib():
         L.cb_plan_destroy.argtypes = [vp]
         L.cb_rhs_stencil.argtypes = [ctypes.POINTER(StencilC), ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_solve.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, vp, vp]
+        L.cb_solve_noalloc.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_apply_derivative.argtypes = [vp, ctypes.POINTER(StencilC), ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_batch_workspace_size.argtypes = [i32]
         L.cb_batch_workspace_size.restype = ctypes.c_size_t
@@ -85,7 +87,7 @@ def lib():
         L.cb_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
         L.cb_plan_get_array.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(i64)]
         L.cb_last_error.restype = ctypes.c_char_p
-        for f in ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
+        for f in ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_solve_noalloc", "cb_apply_derivative",
                   "cb_solve_batched", "cb_batch_build", "cb_batch_launch", "cb_plan_get_info",
                   "cb_plan_get_schedule", "cb_plan_get_array"):
             getattr(L, f).restype = ctypes.c_int
@@ -200,6 +202,19 @@ def solve(plan, b, axis, out=None, stream=None):
         raise ValueError("b and out must have the same layout")
     _check(lib().cb_solve(plan.h, ctypes.byref(g), axis, _dev(b), _dev(out), _stream(stream)))
     return out
+
+
+def solve_noalloc(plan, b, axis, out, stream=None):
+    """cb_solve_noalloc: as solve(), with the partition scratch in the
+    library's fixed per-GPU array (no device allocation; `out` is required)."""
+    g = grid_of(b)
+    if grid_of(out).stride[:] != g.stride[:]:
+        raise ValueError("b and out must have the same layout")
+    _check(lib().cb_solve_noalloc(plan.h, ctypes.byref(g), axis, _dev(b), _dev(out), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # CB_NOALLOC_SCRATCH_BYTES
 
 
 def apply_derivative(plan, stencil, f, axis, out=None, stream=None):
