@@ -8,6 +8,14 @@ right-hand-side stencil, along x, y and z.  One step = the three directions
 Prints ONE JSON line (rank 0).  `value` is GDOF/s (solved unknowns per
 second); `roofline` uses the algorithmic 16 bytes per unknown (read f, write
 f') of the dominant kernel launch, timed with HIP events on the launch stream.
+The same line then summarises the other workloads under their own keys
+(medians of HIP-event timed launches, inputs resident in HBM): a device copy
+(the practical HBM ceiling, `roofline.frac_of_copy`), plain cb_solve along
+x/y/z of the 512^3 grid, the 32^3 and 256^3 grids (derivative and
+interpolation), 4096 lines of n = 8192 in 16 workgroup partitions with the
+16/15 and 8/7 partition comparison, the 512^3 pentadiagonal derivative, the
+batch of 12 uneven grids (FP64 and FP32 + refinement) and the served request
+stream (p50/p99 latency, GDOF/s).  --no-extras prints the headline alone.
 """
 import argparse
 import json
@@ -75,30 +83,46 @@ def scheme_stencil(name, n):
     return cb.Stencil(*schemes.stencil(name, n))
 
 
-def cpu_baseline(f_dev, bands, stencils, seconds=10.0):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(f_dev, bands, stencils, seconds=10.0, runs=5):
     """The FP64 oracle on the host cores, over a bounded sample of the same work:
-    the fused derivative along x, y and z of z-slabs of the grid, repeated
-    until about `seconds` of CPU time have been spent."""
+    the fused derivative along x and y of z-slabs of the grid and along z of
+    y-slabs.  `runs` timed runs of about seconds/runs each; the median rate."""
     import oracle
     f = f_dev.cpu().numpy()
     nz, ny, nx = f.shape
     slab = max(1, nz // 8)
-    sub = np.ascontiguousarray(f[:slab])
-    t_total, dof, reps = 0.0, 0, 0
-    while t_total < seconds:
-        for axis in range(3):
-            st = stencils[axis]
-            src = sub if axis < 2 else np.ascontiguousarray(f[:, :max(1, ny // 8), :])
-            t0 = time.perf_counter()
-            oracle.apply_axis(src, axis, bands, st.lo, st.coefs)
-            t_total += time.perf_counter() - t0
-            dof += src.size
-        reps += 1
-    return {"value": round(dof / t_total / 1e9, 4), "unit": "GDOF/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    srcs = [np.ascontiguousarray(f[:slab]), np.ascontiguousarray(f[:slab]),
+            np.ascontiguousarray(f[:, :max(1, ny // 8), :])]
+    rates, t_all = [], 0.0
+    for _ in range(runs):
+        t_run, dof = 0.0, 0
+        while t_run < seconds / runs:
+            for axis in range(3):
+                st = stencils[axis]
+                t0 = time.perf_counter()
+                oracle.apply_axis(srcs[axis], axis, bands, st.lo, st.coefs)
+                t_run += time.perf_counter() - t0
+                dof += srcs[axis].size
+        rates.append(dof / t_run / 1e9)
+        t_all += t_run
+    return {"value": round(float(np.median(rates)), 4), "unit": "GDOF/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "runs_gdofs": [round(r, 4) for r in rates],
             "sample": "FP64 oracle (banded LU + Woodbury, OpenMP over lines): fused derivative along x and y of "
-                      "%d z-planes and along z of %d y-rows of the %d^3 grid, %d passes, %.1f s"
-                      % (slab, max(1, ny // 8), nx, reps, t_total)}
+                      "%d z-planes and along z of %d y-rows of the %d^3 grid; median of %d runs, %.1f s in all"
+                      % (slab, max(1, ny // 8), nx, runs, t_all)}
 
 
 def headline(args):
@@ -175,7 +199,144 @@ def headline(args):
         res["cpu_baseline"] = cpu_baseline(f, bands, [st, st, st], seconds=args.cpu_seconds)
     for p in set(plans):
         p.close()
+    del f, outs
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        # the other workloads, each summarised under its own key (a failing
+        # leg reports its error and the others still run)
+        steps, warm = 10, 2
+        legs = (("copy_ceiling", lambda: leg_copy(1024, steps, warm)),
+                ("solve_512", lambda: leg_solve(n, steps, warm)),
+                ("small_grids", lambda: leg_small(steps, warm)),
+                ("two_level_8192", lambda: leg_two_level(steps, warm)),
+                ("penta10_512", lambda: leg_penta(n, steps, warm)),
+                ("batched_12_grids", lambda: leg_batched(steps, warm)),
+                ("served", lambda: leg_served(args.serve_requests, args.max_points)))
+        for key, fn in legs:
+            t0 = time.perf_counter()
+            try:
+                res[key] = fn()
+            except Exception as e:  # noqa: BLE001 -- reported in the line, the headline stands
+                res[key] = {"error": "%s: %s" % (type(e).__name__, e)}
+            res[key]["leg_wall_s"] = round(time.perf_counter() - t0, 1)
+            torch.cuda.empty_cache()
+        cp = res["copy_ceiling"].get("gbs")
+        if cp:
+            res["roofline"]["copy_gbs"] = cp
+            res["roofline"]["frac_of_copy"] = round(achieved / cp, 4)
     return res
+
+
+def _median_ms(fn, steps, warmup, stream):
+    dur, _ = _time_launches(fn, steps, warmup, stream)
+    return float(np.median(dur))
+
+
+def leg_solve(n, steps, warmup):
+    """Plain cb_solve (b = stencil(f) precomputed) along x, y, z of the n^3 grid."""
+    dev = torch.device("cuda:0")
+    bands = schemes.bands("tri6")
+    plan = cb.Plan(bands, n)
+    st = scheme_stencil("tri6", n)
+    f, _ = synth.random_modes((n, n, n), seed=0, device=dev)
+    out = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for ax in range(3):
+        b = cb.rhs_stencil(st, f, ax)
+        ms = _median_ms(lambda: cb.solve(plan, b, ax, out=out, stream=stream), steps, warmup, stream)
+        res["xyz"[ax]] = {"ms": round(ms, 4), "gdofs": round(n ** 3 / (ms * 1e-3) / 1e9, 2)}
+        del b
+    plan.close()
+    return {"workload": "%d^3 cyclic tridiagonal (alpha=1/3) cb_solve of b = stencil(f), per direction" % n,
+            "per_direction": res}
+
+
+def leg_copy(mib, steps, warmup):
+    """A plain device copy (torch copy_) of `mib` MiB: the practical HBM ceiling."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    ms = _median_ms(lambda: b.copy_(a), steps, warmup, stream)
+    return {"workload": "device copy of %d MiB (read + write)" % mib, "ms": round(ms, 4),
+            "gbs": round(2 * a.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+
+
+def leg_small(steps, warmup):
+    """32^3 x derivative and 256^3 derivative + collocated-to-staggered interpolation along x, y, z."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for n, axes, kinds in ((32, (0,), ("deriv6",)), (256, (0, 1, 2), ("deriv6", "interp6_c2s"))):
+        f, _ = synth.random_modes((n, n, n), seed=0, device=dev)
+        out = torch.empty_like(f)
+        for kind in kinds:
+            if kind == "deriv6":
+                bands, st = schemes.bands("tri6"), scheme_stencil("tri6", n)
+            else:
+                bands = schemes.bands("interp6")
+                st = cb.Stencil(*schemes.stencil("interp6", n))
+            plan = cb.Plan(bands, n)
+            for ax in axes:
+                ms = _median_ms(lambda: cb.apply_derivative(plan, st, f, ax, out=out, stream=stream), steps, warmup,
+                                stream)
+                res["%d^3 %s %s" % (n, kind, "xyz"[ax])] = {"ms": round(ms, 4),
+                                                             "gdofs": round(n ** 3 / (ms * 1e-3) / 1e9, 2)}
+            plan.close()
+    return {"workload": "32^3 sixth-order derivative along x; 256^3 derivative and interpolation along x, y, z",
+            "runs": res}
+
+
+def leg_two_level(steps, warmup):
+    """64x64 lines of n = 8192 with P = 16 workgroup partitions (cb_solve along x, y and z), and the
+    one-GPU analogue of the power-of-two vs one-less partition comparison: 512-row partitions,
+    P = 16 / 15 and 8 / 7 (n = 512 P), x lines."""
+    dev = torch.device("cuda:0")
+    bands = schemes.bands("tri6")
+    stream = torch.cuda.current_stream()
+    res = {}
+    n, P = 8192, 16
+    plan = cb.Plan(bands, n, partitions=P)
+    for ax in range(3):
+        dims = [64, 64]
+        dims.insert(ax, n)
+        b = synth.random_uniform((dims[2], dims[1], dims[0]), seed=3, device=dev)
+        x = torch.empty_like(b)
+        ms = _median_ms(lambda: cb.solve(plan, b, ax, out=x, stream=stream), steps, warmup, stream)
+        res["n8192_P16_" + "xyz"[ax]] = {"ms": round(ms, 4), "gdofs": round(b.numel() / (ms * 1e-3) / 1e9, 2)}
+    plan.close()
+    scal = {}
+    for P in (16, 15, 8, 7):
+        n = 512 * P
+        plan = cb.Plan(bands, n, partitions=P)
+        b = synth.random_uniform((64, 64, n), seed=4, device=dev)
+        x = torch.empty_like(b)
+        ms = _median_ms(lambda: cb.solve(plan, b, 0, out=x, stream=stream), steps, warmup, stream)
+        info = plan.info()
+        scal["P%d" % P] = {"n": n, "ms": round(ms, 4), "gdofs": round(b.numel() / (ms * 1e-3) / 1e9, 2),
+                           "pcr_steps": info["red_pcr_steps"], "detach_steps": info["red_detach_steps"]}
+        plan.close()
+    return {"workload": "4096 lines of n=8192, P=16 workgroup partitions, cb_solve per axis; 512-row partitions "
+                        "at P = 16/15 and 8/7", "runs": res, "pow2_vs_one_less": scal}
+
+
+def leg_penta(n, steps, warmup):
+    """n^3 tenth-order pentadiagonal compact derivative (alpha=1/2, beta=1/20) along x, y, z."""
+    dev = torch.device("cuda:0")
+    bands = schemes.bands("penta10")
+    st = scheme_stencil("penta10", n)
+    plan = cb.Plan(bands, n)
+    f, _ = synth.random_modes((n, n, n), seed=1, device=dev)
+    out = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for ax in range(3):
+        ms = _median_ms(lambda: cb.apply_derivative(plan, st, f, ax, out=out, stream=stream), steps, warmup, stream)
+        res["xyz"[ax]] = {"ms": round(ms, 4), "gdofs": round(n ** 3 / (ms * 1e-3) / 1e9, 2)}
+    plan.close()
+    return {"workload": "%d^3 tenth-order cyclic pentadiagonal compact derivative fused with its stencil" % n,
+            "per_direction": res}
 
 
 def _time_launches(fn, steps, warmup, stream):
@@ -236,9 +397,11 @@ def mode_penta_z(args):
             "dtype": "f64", "config": {"workload": "%d^3, alpha=1/2 beta=1/20" % n}}
 
 
-def mode_batched(args):
-    """12 uneven periodic grids x 3 axes in one batched launch per kernel class (one workgroup per
-    tile; the persistent work-queue form is timed beside it): FP32+refinement vs FP64."""
+def batched_runs(variants, steps, warmup, batch_ctas=-1, tune=False, extras=True):
+    """12 uneven periodic grids x 3 axes in one batched launch per kernel class, for each
+    (key, precision, refine_iters) variant; with `extras` the persistent work-queue form and a
+    graph replay of the same launches are timed too.  FP32 variants report their max relative
+    difference to the FP64 outputs."""
     dev = torch.device("cuda:0")
     shapes = synth.grid_batch_shapes(seed=0, count=12)
     bands = schemes.bands("tri6")
@@ -247,23 +410,20 @@ def mode_batched(args):
         f, _ = synth.random_modes((nz, ny, nx), seed=gi, device=dev)
         fields.append(f)
     out = {}
-    # FP64, then FP32 with the library's refinement count (the fewest
-    # iterations that reach 1e-12 by its condition-number rule: one for this
-    # scheme) and with two (the FP64 floor)
-    for key, prec, iters in (("fp64", "fp64", 0), ("fp32_refine", "fp32_refine", 0), ("fp32_refine2", "fp32_refine", 2)):
+    for key, prec, iters in variants:
         plans, items = {}, []
         for f in fields:
             for ax in range(3):
                 n = f.shape[2 - ax]
-                # --tune: the autotuner's choice (rows per lane, interior solve,
+                # tune: the autotuner's choice (rows per lane, interior solve,
                 # ...) per grid shape and axis; else one default plan per n
-                key_p = (n, tuple(f.shape), ax) if args.tune else n
+                key_p = (n, tuple(f.shape), ax) if tune else n
                 if key_p not in plans:
                     st = scheme_stencil("tri6", n)
-                    if args.tune:
-                        from paper_2101_02286_amd import tune
-                        best, _ = tune.tune(bands, n, f, ax, stencil=st, precision=prec, refine_iters=iters,
-                                            reps=3, cache=None, one_partition=True)
+                    if tune:
+                        from paper_2101_02286_amd import tune as tuner
+                        best, _ = tuner.tune(bands, n, f, ax, stencil=st, precision=prec, refine_iters=iters,
+                                             reps=3, cache=None, one_partition=True)
                         plans[key_p] = (cb.Plan(bands, n, precision=prec, refine_iters=iters, **best), st)
                     else:
                         plans[key_p] = (cb.Plan(bands, n, precision=prec, refine_iters=iters), st)
@@ -281,68 +441,116 @@ def mode_batched(args):
         stream = torch.cuda.current_stream()
         cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), need,
                                           cb.ctypes.c_void_p(stream.cuda_stream)))
-        launch = lambda: cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), args.batch_ctas,
+        launch = lambda: cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), batch_ctas,
                                                             cb.ctypes.c_void_p(stream.cuda_stream)))
-        dur, wall = _time_launches(launch, args.steps, args.warmup, stream)
+        dur, wall = _time_launches(launch, steps, warmup, stream)
         dof = sum(f.numel() for f in fields) * 3
-        ms = float(dur.mean())
-        # the persistent work-queue form of the same launches, for comparison
-        qlaunch = lambda: cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), 0,
-                                                             cb.ctypes.c_void_p(stream.cuda_stream)))
-        qdur, _ = _time_launches(qlaunch, args.steps, args.warmup, stream)
-        qms = float(qdur.mean())
-        # the same launches captured once in a HIP graph and replayed
-        gs = torch.cuda.Stream()
-        gs.wait_stream(stream)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=gs):
-            cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), args.batch_ctas,
-                                               cb.ctypes.c_void_p(gs.cuda_stream)))
-        torch.cuda.synchronize()
-        gdur, _ = _time_launches(g.replay, args.steps, args.warmup, torch.cuda.current_stream())
-        gms = float(gdur.mean())
-        out[key] = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
-                     "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1), "items": len(items),
-                     "graph_replay_ms": round(gms, 4), "graph_replay_gdofs": round(dof / (gms * 1e-3) / 1e9, 2),
-                     "refine_iters": sorted({it[0].info()["refine_iters"] for it in items}),
-                     "persistent_queue_gdofs": round(dof / (qms * 1e-3) / 1e9, 2),
-                     "outputs": [it[3] for it in items]}
+        ms = float(np.median(dur))
+        r = {"ms": round(ms, 4), "gdofs": round(dof / (ms * 1e-3) / 1e9, 2),
+             "hbm_gbs_algorithmic": round(16 * dof / (ms * 1e-3) / 1e9, 1), "items": len(items),
+             "refine_iters": sorted({it[0].info()["refine_iters"] for it in items}),
+             "outputs": [it[3] for it in items]}
+        if extras:
+            # the persistent work-queue form of the same launches
+            qlaunch = lambda: cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), 0,
+                                                                 cb.ctypes.c_void_p(stream.cuda_stream)))
+            qdur, _ = _time_launches(qlaunch, steps, warmup, stream)
+            r["persistent_queue_gdofs"] = round(dof / (float(np.median(qdur)) * 1e-3) / 1e9, 2)
+            # the same launches captured once in a HIP graph and replayed
+            gs = torch.cuda.Stream()
+            gs.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=gs):
+                cb._check(cb.lib().cb_batch_launch(cb.ctypes.c_void_p(ws.data_ptr()), batch_ctas,
+                                                   cb.ctypes.c_void_p(gs.cuda_stream)))
+            torch.cuda.synchronize()
+            gdur, _ = _time_launches(g.replay, steps, warmup, torch.cuda.current_stream())
+            gms = float(np.median(gdur))
+            r["graph_replay_ms"] = round(gms, 4)
+            r["graph_replay_gdofs"] = round(dof / (gms * 1e-3) / 1e9, 2)
+        out[key] = r
+        for pl, _st in plans.values():
+            pl.close()
     # accuracy of the FP32+refinement outputs against the FP64 outputs
     o64s = out["fp64"].pop("outputs")
-    for key in ("fp32_refine", "fp32_refine2"):
+    for key in out:
+        if key == "fp64":
+            continue
         worst = 0.0
         for o64, o32 in zip(o64s, out[key].pop("outputs")):
             worst = max(worst, float(((o64 - o32).abs().max() / o64.abs().max()).item()))
         out[key]["max_rel_diff_vs_fp64"] = worst
+    return out, shapes
+
+
+def mode_batched(args):
+    """12 uneven periodic grids x 3 axes in one batched launch per kernel class (one workgroup per
+    tile; the persistent work-queue form is timed beside it): FP32+refinement vs FP64."""
+    # FP64, then FP32 with the library's refinement count (the fewest
+    # iterations that reach 1e-12 by its condition-number rule: one for this
+    # scheme) and with two (the FP64 floor)
+    out, shapes = batched_runs((("fp64", "fp64", 0), ("fp32_refine", "fp32_refine", 0),
+                                ("fp32_refine2", "fp32_refine", 2)), args.steps, args.warmup, args.batch_ctas,
+                               args.tune)
     return {"metric": "GDOF/s, 12 uneven grids x 3 axes in one batched launch per kernel class", "fp64": out["fp64"],
             "fp32_refine": out["fp32_refine"], "fp32_refine2": out["fp32_refine2"],
             "config": {"workload": "grids %s" % shapes, "autotuned": bool(args.tune)}}
 
 
+def leg_batched(steps, warmup):
+    out, shapes = batched_runs((("fp64", "fp64", 0), ("fp32_refine", "fp32_refine", 0)), steps, warmup,
+                               extras=False)
+    return {"workload": "12 uneven periodic grids %s x 3 axes, sixth-order derivative, one workgroup per tile"
+                        % [list(map(int, s)) for s in shapes], "fp64": out["fp64"], "fp32_refine": out["fp32_refine"]}
+
+
+def serve_run(rate, precision, count, max_points, budget_gb=0.0, seed=11):
+    """One served Poisson stream (inputs staged in HBM and plans factorised before the clock)."""
+    from paper_2101_02286_amd.serve import GpuExecutor, Server, poisson_requests
+    reqs = poisson_requests(count, rate_hz=rate, seed=seed, max_points=max_points)
+    ex = GpuExecutor(slots=8, precision=precision)
+    ex.stage(reqs)
+    srv = Server(ex, hbm_budget=budget_gb * (1 << 30) if budget_gb else None, slots=8, max_batch=4)
+    st = srv.run(reqs)
+    st["rate_hz"] = rate
+    st["precision"] = precision
+    del ex
+    torch.cuda.empty_cache()
+    return st
+
+
+def leg_served(count, max_points):
+    """The served stream at a moderate Poisson rate and all at once (saturation), FP32 + refinement
+    and plain FP64 on the same requests."""
+    for prec in ("fp32_refine", "fp64"):  # warm-up: load every kernel once, untimed
+        serve_run(1e9, prec, 16, max_points, seed=5)
+    res = {}
+    for rate in (400.0, 1e9):
+        for prec in ("fp32_refine", "fp64"):
+            st = serve_run(rate, prec, count, max_points)
+            res["%s@%s" % (prec, "all_at_once" if rate >= 1e9 else "%gHz" % rate)] = {
+                k: (round(v, 3) if isinstance(v, float) else v)
+                for k, v in st.items() if k in ("requests", "p50_ms", "p99_ms", "gdofs", "span_s",
+                                                 "max_inflight_batches", "batches", "max_batch_requests")}
+    return {"workload": "%d requests, sides log-uniform [32,1024], <= %.2g points, random axis, tri6/penta10"
+                        % (count, max_points), "runs": res}
+
+
 def mode_serve(args):
     """Poisson request stream served with continuous batching (FP32+refinement)."""
-    from paper_2101_02286_amd.serve import GpuExecutor, Server, poisson_requests
     # 8 stream slots and at most 4 requests per batched launch: small batches
     # keep the slots balanced (measured: saturation p50 11.6 ms vs 21 ms with
     # 4 slots x 16 requests)
-    def run(rate, precision, count=args.requests):
-        reqs = poisson_requests(count, rate_hz=rate, seed=11, max_points=args.max_points)
-        ex = GpuExecutor(slots=8, precision=precision)
-        ex.stage(reqs)  # inputs resident in HBM and plans factorised before the clock starts
-        srv = Server(ex, hbm_budget=args.budget_gb * (1 << 30) if args.budget_gb else None, slots=8, max_batch=4)
-        st = srv.run(reqs)
-        st["rate_hz"] = rate
-        st["precision"] = precision
-        return st
-
     for prec in ("fp32_refine", "fp64"):  # warm-up: load every kernel once, untimed
-        run(max(args.rates), prec, count=24)
-    res = [run(rate, "fp32_refine") for rate in args.rates]
-    fp64 = run(max(args.rates), "fp64")  # the same stream in plain FP64 at the highest rate
-    return {"metric": "served p50/p99 latency and GDOF/s", "runs": res,
-            "saturation_gdofs": round(max(r["gdofs"] for r in res), 2), "fp64_at_highest_rate": fp64,
+        serve_run(max(args.rates), prec, 24, args.max_points, args.budget_gb)
+    res = [serve_run(rate, "fp32_refine", args.requests, args.max_points, args.budget_gb) for rate in args.rates]
+    fp64 = [serve_run(rate, "fp64", args.requests, args.max_points, args.budget_gb) for rate in args.rates]
+    return {"metric": "served p50/p99 latency and GDOF/s", "runs": res, "runs_fp64": fp64,
+            "saturation_gdofs": round(max(r["gdofs"] for r in res), 2),
+            "saturation_gdofs_fp64": round(max(r["gdofs"] for r in fp64), 2),
             "config": {"workload": "Poisson stream, sides log-uniform [32,1024], <= %.2g points, "
-                                   "tri6/penta10, FP32+refinement (automatic count: 1 tri6, 2 penta10)" % args.max_points}}
+                                   "tri6/penta10, FP32+refinement (automatic count: 1 tri6, 2 penta10) and FP64 "
+                                   "at the same rates" % args.max_points}}
 
 
 def mode_copy(args):
@@ -363,7 +571,7 @@ def main():
                     choices=["headline", "two_level", "penta_z", "batched", "serve", "copy"])
     ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 800.0, 3200.0, 1e9],
                     help="Poisson arrival rates (requests/s); a huge rate = all requests at once (saturation)")
-    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--batch-ctas", type=int, default=-1,
                     help="batched launches: < 0 one workgroup per tile (default); 0 persistent queue with all "
                          "workgroups that fit; > 0 persistent queue with at most that many")
@@ -376,6 +584,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only (skip the summaries of the other workloads)")
+    ap.add_argument("--serve-requests", type=int, default=240,
+                    help="requests per served run in the default (headline) line")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape per direction first")
     args = ap.parse_args()

@@ -248,6 +248,9 @@ typedef struct {
   int32_t partitions_strided;    /* workgroup partitions of strided launches
                                     (FP64 one-partition plans with n > 4096
                                     split strided lines into ~1024-row parts) */
+  int32_t boundary_window;       /* P > 1: rows at each end of an interior
+                                    block that phase A reads (the kept part
+                                    of the boundary rows of D_i^{-1}) */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 
@@ -272,6 +275,9 @@ cb_status cb_plan_get_schedule(cb_plan_t plan, int32_t *out, int32_t cap, int32_
  *   8 reduced-solve program: term ranges [phases][P+1]
  *   9 its source rows per term          10 its matrices per term [r][r]
  *  11 segment shape: S, L, M, r, Tint, Tred, elimination, uniform, cyclic
+ *  12 boundary rows of D_i^{-1} [P][2][r][boundary_window]: rows 0..r-1 over
+ *     the block's first boundary_window rows, then rows N_i-r..N_i-1 over
+ *     its last boundary_window rows
  * Writes min(cap, size) values; *len receives the full size. */
 cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *out, int64_t cap,
                             int64_t *len);

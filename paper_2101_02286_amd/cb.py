@@ -60,7 +60,8 @@ class PlanInfo(ctypes.Structure):
                                          ("lanes_strided", ctypes.c_int32),
                                          ("interior_elimination", ctypes.c_int32),
                                          ("interior_elimination_strided", ctypes.c_int32),
-                                         ("partitions_strided", ctypes.c_int32)]
+                                         ("partitions_strided", ctypes.c_int32),
+                                         ("boundary_window", ctypes.c_int32)]
 
 
 def lib():

@@ -130,8 +130,9 @@ cb_status upload(Plan &p) {
     so[i].w32 = ar.add(to_f32(s.wf));
   }
   const size_t o_bands = ar.add(p.bands);
-  size_t o_wg = 0, o_sr = 0, o_sroff = 0, o_ltut = 0, o_ro = 0, o_src = 0, o_mats = 0;
+  size_t o_wg = 0, o_sr = 0, o_sroff = 0, o_ltut = 0, o_ro = 0, o_src = 0, o_mats = 0, o_bfun = 0;
   if (p.P > 1) {
+    o_bfun = ar.add(p.bfun);
     o_wg = ar.add(p.wg_start);
     o_sr = ar.add(p.SRg);
     o_sroff = ar.add(p.SRg_off);
@@ -190,6 +191,7 @@ cb_status upload(Plan &p) {
     p.d_row_off = reinterpret_cast<const int *>(base + o_ro);
     p.d_src = reinterpret_cast<const int *>(base + o_src);
     p.d_mats = reinterpret_cast<const double *>(base + o_mats);
+    p.d_bfun = reinterpret_cast<const double *>(base + o_bfun);
   }
   if (p.strided_wg) {
     cb_status sw = upload(*p.strided_wg);
@@ -455,6 +457,13 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.row_off = p.d_row_off;
   a.src = p.d_src;
   a.mats = p.d_mats;
+  a.bfun = p.d_bfun;
+  a.kw = p.Kw;
+  a.wave_local = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 1 : 0;
+  // phase A: 256 threads; a unit-stride line per wavefront (consecutive rows
+  // in consecutive lanes), strided lines 64 adjacent ones per row access
+  constexpr int kNTA = 256;
+  const int WA = mode == MODE_X ? kNTA / 64 : 64;
   const size_t sbytes = (size_t)g.nlines * p.P * 3 * p.R * sizeof(double);
   void *scratch = nullptr;
   hipError_t e = hipSuccess;
@@ -473,11 +482,12 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   }
   a.scratch = static_cast<double *>(scratch);
   const int64_t tiles = (g.nlines + W - 1) / W;
+  const int64_t tiles_a = (g.nlines + WA - 1) / WA;
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
-  const size_t lds_a = ((size_t)a.stage_off_a + (size_t)W * pitch) * sizeof(double);
+  const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
   const size_t lds_c = ((size_t)a.stage_off_c + (size_t)W * pitch) * sizeof(double);
-  e = hipLaunchKernel(k->fn_a, grid, dim3(NT), args, lds_a, stream);
+  e = hipLaunchKernel(k->fn_a, dim3((unsigned)tiles_a, (unsigned)p.P), dim3(kNTA), args, lds_a, stream);
   if (e == hipSuccess)
     e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
   if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
@@ -928,6 +938,7 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->interior_elimination = p.segs.empty() ? 0 : p.segs[0].ilu;
   info->interior_elimination_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].ilu;
   info->partitions_strided = p.strided_wg ? p.strided_wg->P : p.P;
+  info->boundary_window = p.Kw;
   return CB_OK;
 }
 
@@ -965,6 +976,7 @@ cb_status cb_plan_get_array(cb_plan_t plan, int32_t seg, int32_t which, double *
     case 11: v = {(double)s.S, (double)s.L, (double)s.M, (double)s.R, (double)s.Tint, (double)s.Tred,
                   (double)s.ilu, (double)s.uniform, (double)s.cyclic};
       break;
+    case 12: v = p.bfun; break;
     default: return fail(CB_ERR_INVALID_ARG, "unknown array id");
   }
   *len = (int64_t)v.size();

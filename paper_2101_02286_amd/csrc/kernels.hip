@@ -63,8 +63,11 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
                                                   int &start, int &m, double *coef_lds, double *tb,
                                                   const double (&xi)[R], const double (&xi1)[R]) {
+  // Every global read that does not depend on the data (lane type, the
+  // couplings of the block's end rows to the interface values, the
+  // coefficient blocks) is issued together with the data, so the workgroup
+  // waits for one round trip to memory instead of several in a row.
   const SegDev &sg = a.segs[part];
-  if (a.coef_lds) stage_coef<double>(sg, coef_lds, p.tid, blockDim.x);
   lane_rows(sg.S, p.lgL, p.l, start, m);
   const int type = sg.lane_type[p.l];
   const int S = sg.S;
@@ -72,10 +75,9 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   const int64_t row0 = seg0 + start;
   const bool staged = MODE == MODE_X && tb != nullptr;
   constexpr int QQ = Q > 0 ? Q : 1;
-  double gp[QQ], gn[QQ];  // staged stencil: halo rows beyond D_i's ends
+  double gp[QQ], gn[QQ];  // stencil halo rows beyond D_i's ends
+  double t[M];
   if (staged) {
-    // the block-end halo rows (first and last lanes) are read from global
-    // memory together with the tile, so their latency overlaps it
     if (Q > 0) {
 #pragma unroll
       for (int i = 0; i < QQ; ++i) {
@@ -88,24 +90,62 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
       }
     }
     const double *lin = a.in + base + seg0;
-    double t[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int e = p.l + k * p.L;
       t[k] = (active && e < S) ? __builtin_nontemporal_load(lin + e) : 0.0;
     }
+  } else {
+    const double *in = a.in + base + row0 * a.rs;
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
+    if (Q > 0) {
+#pragma unroll
+      for (int i = 0; i < QQ; ++i) {
+        int64_t r0 = seg0 - QQ + i, r1 = a.wg_start[part + 1] + i;
+        r0 = r0 < 0 ? r0 + a.n : r0;
+        r1 = r1 >= a.n ? r1 - a.n : r1;
+        gp[i] = (active && p.l == 0) ? a.in[base + r0 * a.rs] : 0.0;
+        gn[i] = (active && p.l == p.L - 1) ? a.in[base + r1 * a.rs] : 0.0;
+      }
+    }
+  }
+  // Eq. (9): the block's first R rows couple to x~_i (first lane), its last R
+  // rows to x~_{i+1} (last lane); those terms move to the right-hand side
+  double head[R], tail[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) head[c] = tail[c] = 0.0;
+  if (ADJ) {
+    constexpr int W2 = 2 * R + 1;
+    if (p.l == 0) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {  // row c of D_i
+        const double *bd = a.bands + (seg0 + c) * W2;
+#pragma unroll
+        for (int o = -R; o < 0; ++o)
+          if (c + o < 0) head[c] += bd[o + R] * xi[R + c + o];
+      }
+    }
+    if (p.l == p.L - 1) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {  // row S-R+c of D_i
+        const double *bd = a.bands + (seg0 + S - R + c) * W2;
+#pragma unroll
+        for (int o = 1; o <= R; ++o)
+          if (c + o >= R) tail[c] += bd[o + R] * xi1[c + o - R];
+      }
+    }
+  }
+  if (a.coef_lds) stage_coef<double>(sg, coef_lds, p.tid, blockDim.x);
+  if (staged) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const int e = p.l + k * p.L;
       if (e < S) tb[tile_at<M>(e)] = t[k];
     }
-    __syncthreads();
+    xc.sync();  // the line's tile is read and written by its own lanes only
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = k < m ? tb[tile_at<M>(start + k)] : 0.0;
-  } else {
-    const double *in = a.in + base + row0 * a.rs;
-#pragma unroll
-    for (int k = 0; k < M; ++k) v[k] = (active && k < m) ? in[k * a.rs] : 0.0;
   }
   if (Q > 0) {  // fused stencil; the halo at the block's ends comes from global memory
     double fp[QQ], fn[QQ];
@@ -120,20 +160,11 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
       halo<QQ, M>(v, m, false, p, xc, fp, fn);
       if (p.l == 0) {
 #pragma unroll
-        for (int i = 0; i < QQ; ++i) {
-          int64_t r = seg0 - QQ + i;
-          r = r < 0 ? r + a.n : r;
-          fp[i] = active ? a.in[base + r * a.rs] : 0.0;
-        }
+        for (int i = 0; i < QQ; ++i) fp[i] = gp[i];
       }
       if (p.l == p.L - 1) {
-        const int64_t end = a.wg_start[part + 1];
 #pragma unroll
-        for (int i = 0; i < QQ; ++i) {
-          int64_t r = end + i;
-          r = r >= a.n ? r - a.n : r;
-          fn[i] = active ? a.in[base + r * a.rs] : 0.0;
-        }
+        for (int i = 0; i < QQ; ++i) fn[i] = gn[i];
       }
     }
     double bb[M];
@@ -148,21 +179,14 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     for (int k = 0; k < M; ++k) v[k] = bb[k];
   }
   if (ADJ) {
-    constexpr int W2 = 2 * R + 1;
+    if (p.l == 0) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const int sr = start + k;  // row within D_i
-      if (k < m && (sr < R || sr >= S - R)) {
-        const double *bd = a.bands + (seg0 + sr) * W2;
+      for (int c = 0; c < R; ++c) v[c] -= head[c];
+    }
+    if (p.l == p.L - 1) {
 #pragma unroll
-        for (int o = -R; o <= R; ++o) {
-          const int t = sr + o;
-          // select among the interface values (a plain two-way choice here
-          // becomes a runtime-indexed stack array)
-          if (t < 0) v[k] -= bd[o + R] * select_idx(xi, R + t);        // row R+t of x~_i
-          else if (t >= S) v[k] -= bd[o + R] * select_idx(xi1, t - S);  // row t-S of x~_{i+1}
-        }
-      }
+      for (int k = 0; k < M; ++k)
+        if (k >= m - R && k < m) v[k] -= select_idx(tail, k - (m - R));
     }
   }
   if (a.coef_lds)
@@ -178,54 +202,124 @@ constexpr int wg_max_threads() {
   return (MODE == MODE_X && M > 8) ? 512 : 1024;
 }
 
-template <int R, int M, int MODE, int Q, bool ILU>
-__global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_a(const WgArgs a) {
+// Phase A: what a partition shares with the others.  Only b~_i (the RHS of
+// its R interface rows) and the first and last R rows of y_i = D_i^{-1} b_i
+// enter the reduced system (Eq. (21); the sparsity of L~ and U~), and those
+// rows of y_i are dot products of b_i with the boundary rows of D_i^{-1}
+// that the plan holds over a window of kw rows at each end of D_i.  So the
+// phase reads only those windows (and the interface rows), computing b on
+// the fly when the stencil is fused.  T threads share one (line, partition)
+// and take every T-th row of both windows, all loads issued before the
+// first product.  Unit-stride lines: one wavefront each (consecutive rows in
+// consecutive lanes), summed by a shuffle tree.  Strided lines: 4 threads
+// each, 64 adjacent lines per workgroup (one contiguous row segment per
+// access), summed through LDS.  Both sums run in a fixed order.
+template <int R, int MODE, int Q>
+__global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   extern __shared__ double smem[];
-  LanePos p;
-  int64_t line, base;
-  bool active;
-  wg_setup<R, M, MODE>(a, p, line, active, base);
-  Xchg xc{smem, (Q > R ? 2 * Q : 2 * R), (int)blockDim.x, 0, true};
+  constexpr int NTA = 256;
+  constexpr int T = MODE == MODE_X ? 64 : NTA / 64;
+  constexpr int WA = NTA / T;  // lines per workgroup
+  const int tid = threadIdx.x;
+  const int li = MODE == MODE_X ? tid / T : tid % WA;
+  const int t = MODE == MODE_X ? tid % T : tid / WA;
   const int part = blockIdx.y;
-  // inputs of the partition's interface rows g0..g0+R-1 (with the +-Q
-  // stencil neighbours), read before the interior solve so their latency
-  // overlaps it
-  constexpr int QI = Q;
-  double iv[R + 2 * QI];
+  const int64_t line = (int64_t)blockIdx.x * WA + li;
+  const bool active = line < a.nlines;
+  const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
+  const uint32_t line32 = active ? (uint32_t)line : 0u;
+  const uint32_t lv = fd.div(line32), lu = line32 - lv * a.nudiv.d;
+  const double *in = a.in + (int64_t)lu * a.su + (int64_t)lv * a.sv;
   const int64_t g0 = a.wg_start[part];
+  const int64_t d0 = g0 + R;  // first row of D_i
+  const int N = (int)(a.wg_start[part + 1] - d0);
+  const int K = a.kw;
+  const double *gf = a.bfun + (size_t)part * 2 * R * K, *gl = gf + (size_t)R * K;
+  // b of row j of D_i (j < 0: the interface rows), from the fused stencil or
+  // the input itself
+  auto rhs = [&](int64_t j) -> double {
+    if constexpr (Q > 0) {
+      double acc = 0.0;
 #pragma unroll
-  for (int j = 0; j < R + 2 * QI; ++j) {
-    int64_t r = g0 - QI + j;
-    r = r < 0 ? r + a.n : (r >= a.n ? r - a.n : r);
-    iv[j] = (active && p.l == 0) ? a.in[base + r * a.rs] : 0.0;
-  }
-  double v[M];
-  int start, m;
-  const double none[R] = {};
-  wg_solve_interior<R, M, MODE, Q, false, ILU>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_a,
-                                          a.stage_x ? smem + a.stage_off_a + (size_t)p.li * a.stage_pitch : nullptr,
-                                          none, none);
-  if (!active) return;
-  double *sc = a.scratch + (line * a.P + part) * 3 * R;
-  if (p.l == 0) {
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      double bt;
-      if constexpr (Q > 0) {  // stencil at the partition's interface row g0 + c
-        bt = 0.0;
-#pragma unroll
-        for (int q = -QI; q <= QI; ++q) bt += a.stc[q + 3] * iv[c + q + QI];
-      } else {
-        bt = iv[c];
+      for (int q = -Q; q <= Q; ++q) {
+        int64_t r = d0 + j + q;
+        r = r < 0 ? r + a.n : (r >= a.n ? r - a.n : r);
+        acc += a.stc[q + 3] * in[r * a.rs];
       }
-      sc[c] = bt;         // b~_i
-      sc[R + c] = v[c];   // first R rows of y_i
+      return acc;
+    } else {
+      return in[(d0 + j) * a.rs];
+    }
+  };
+  // interface rows first (their loads overlap the windows')
+  double bt[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) bt[c] = (active && t == 0) ? rhs(c - R) : 0.0;
+  double yf[R], yl[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) yf[c] = yl[c] = 0.0;
+  if (active) {
+    // rows t, t+T, ... of the first window [0, K) and of the last [N-K, N)
+    constexpr int CH = MODE == MODE_X ? 2 : 12;  // rows per thread and window issued together
+    for (int j0 = 0; j0 < K; j0 += CH * T) {
+      double bf[CH], bl[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int j = j0 + u * T + t;
+        bf[u] = j < K ? rhs(j) : 0.0;
+        bl[u] = j < K ? rhs(N - K + j) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int j = j0 + u * T + t;
+        if (j < K) {
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            yf[c] += gf[c * K + j] * bf[u];
+            yl[c] += gl[c * K + j] * bl[u];
+          }
+        }
+      }
     }
   }
-  if (p.l == p.L - 1) {
-    const int nl = m;
+  if (MODE == MODE_X) {
+    // the wavefront's 64 partial sums, by a shuffle tree
 #pragma unroll
-    for (int c = 0; c < R; ++c) sc[2 * R + c] = select_idx(v, nl - R + c);  // last R rows of y_i
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        yf[c] += __shfl_xor(yf[c], off, 64);
+        yl[c] += __shfl_xor(yl[c], off, 64);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      smem[(size_t)c * NTA + tid] = yf[c];
+      smem[(size_t)(R + c) * NTA + tid] = yl[c];
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        double sf = 0.0, sl = 0.0;
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+          sf += smem[(size_t)c * NTA + u * WA + li];
+          sl += smem[(size_t)(R + c) * NTA + u * WA + li];
+        }
+        yf[c] = sf;
+        yl[c] = sl;
+      }
+    }
+  }
+  if (t != 0 || !active) return;
+  double *sc = a.scratch + (line * a.P + part) * 3 * R;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    sc[c] = bt[c];           // b~_i: interface row g0 + c
+    sc[R + c] = yf[c];       // first R rows of y_i
+    sc[2 * R + c] = yl[c];   // last R rows of y_i
   }
 }
 
@@ -326,7 +420,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
       xi1[r] = s1[r];
     }
   }
-  Xchg xc{smem, RS, NT, 0, true};
+  Xchg xc{smem, RS, NT, 0, a.wave_local == 0};
   double v[M];
   int start, m;
   double *tb = a.stage_x ? smem + a.stage_off_c + (size_t)p.li * a.stage_pitch : nullptr;
@@ -336,11 +430,11 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
   if (MODE == MODE_X && tb != nullptr) {
     // mirror of the staged load: every lane has finished reading the tile
     // (its stencil halo) before any lane overwrites it
-    __syncthreads();
+    xc.sync();
 #pragma unroll
     for (int k = 0; k < M; ++k)
       if (k < m) tb[tile_at<M>(start + k)] = v[k];
-    __syncthreads();
+    xc.sync();
     const int S = a.segs[part].S;
     double *lout = a.out + base + seg0;
 #pragma unroll
@@ -415,7 +509,7 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
 }
 
 #define CB_WG_INST(R, M, MODE, Q, ILU)                                                                 \
-  {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, M, MODE, Q, ILU>,             \
+  {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, MODE, Q>,                      \
    (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q, ILU>}
 #define CB_WG_I(R, M, MODE, Q) CB_WG_INST(R, M, MODE, Q, false), CB_WG_INST(R, M, MODE, Q, true)
 #define CB_WG_Q(R, M, MODE) CB_WG_I(R, M, MODE, 0), CB_WG_I(R, M, MODE, 2), CB_WG_I(R, M, MODE, 3)

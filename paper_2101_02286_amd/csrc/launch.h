@@ -65,6 +65,10 @@ struct WgArgs {
   const double *LtUt;        // [P][2][R][R]
   const int *row_off, *src;  // reduced program
   const double *mats;
+  const double *bfun;        // [P][2][R][kw] boundary rows of D_i^{-1} (phase A)
+  int kw;                    // their window length
+  int wave_local;            // phase C: every line lies in one wavefront (its
+                             // exchanges need only wavefront-local ordering)
 };
 
 struct StencilArgs {

@@ -619,6 +619,80 @@ cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, do
   return CB_OK;
 }
 
+// --------------------------------------- boundary rows of D_i^{-1} (Sec. 4) --
+// The partitions exchange only b~_i and the first and last R rows of
+// y_i = D_i^{-1} b_i (Eq. (21); L~ and U~ touch nothing else).  Those rows
+// are fixed linear functionals of b_i: rows 0..R-1 and N-R..N-1 of D_i^{-1}.
+// They are rows of the inverse, i.e. solutions of D_i^T g = e_a, computed by
+// banded elimination of D_i^T.  For the diagonally dominant compact schemes
+// their entries decay geometrically away from the diagonal, so each is kept
+// over a window at its own end of D_i: the window is the shortest one whose
+// omitted entries sum, in absolute value, to at most 2^-56 of the row's
+// absolute sum (below the rounding of the dot product itself).  One window
+// length Kw serves every partition and row; Kw <= min N_i.
+cb_status boundary_rows(int P, int R, const std::vector<int> &st, const std::function<double(int, int)> &coef,
+                        int &Kw, std::vector<double> &out, std::string &msg) {
+  const int W = 2 * R + 1;
+  const double rel = std::ldexp(1.0, -56);
+  std::vector<std::vector<double>> rows((size_t)P * 2 * R);
+  int kmax = 1, nmin = 1 << 30;
+  for (int i = 0; i < P; ++i) {
+    const int s0 = st[i] + R, N = st[i + 1] - s0;
+    nmin = std::min(nmin, N);
+    // band of D_i^T: D^T[j][j+o] = D[j+o][j]
+    std::vector<double> bt((size_t)N * W, 0.0);
+    for (int j = 0; j < N; ++j)
+      for (int o = -R; o <= R; ++o)
+        if (j + o >= 0 && j + o < N) bt[(size_t)j * W + o + R] = coef(s0 + j + o, -o);
+    std::vector<double> lu((size_t)N * 2 * R), dv(N);
+    cb_status s = lane_lu(N, R, bt, lu.data(), dv.data(), msg);
+    if (s != CB_OK) {
+      msg = "boundary rows of an interior block: " + msg;
+      return s;
+    }
+    for (int end = 0; end < 2; ++end)
+      for (int a = 0; a < R; ++a) {
+        std::vector<double> g(N, 0.0);
+        const int row = end == 0 ? a : N - R + a;
+        g[row] = 1.0;
+        for (int j = 1; j < N; ++j)
+          for (int q = 1; q <= R; ++q)
+            if (j - q >= 0) g[j] -= lu[(size_t)j * 2 * R + q - 1] * g[j - q];
+        for (int j = N - 1; j >= 0; --j) {
+          double acc = g[j] * dv[j];
+          for (int q = 1; q <= R; ++q)
+            if (j + q < N) acc -= lu[(size_t)j * 2 * R + R + q - 1] * g[j + q];
+          g[j] = acc;
+        }
+        double sum = 0.0;
+        for (double v : g) sum += std::fabs(v);
+        // shortest window at this end whose omitted entries stay below rel * sum
+        double omitted = 0.0;
+        int k = N;
+        for (int c = N - 1; c >= 1; --c) {  // c = window length if entries beyond it are omitted
+          const double v = std::fabs(end == 0 ? g[c] : g[N - 1 - c]);
+          if (omitted + v > rel * sum) break;
+          omitted += v;
+          k = c;
+        }
+        kmax = std::max(kmax, k);
+        rows[((size_t)i * 2 + end) * R + a] = std::move(g);
+      }
+  }
+  Kw = std::min(kmax, nmin);
+  out.assign((size_t)P * 2 * R * Kw, 0.0);
+  for (int i = 0; i < P; ++i) {
+    const int N = st[i + 1] - st[i] - R;
+    for (int end = 0; end < 2; ++end)
+      for (int a = 0; a < R; ++a) {
+        const std::vector<double> &g = rows[((size_t)i * 2 + end) * R + a];
+        double *o = out.data() + (((size_t)i * 2 + end) * R + a) * Kw;
+        for (int j = 0; j < Kw; ++j) o[j] = g[end == 0 ? j : N - Kw + j];
+      }
+  }
+  return CB_OK;
+}
+
 cb_status build_segment(int S, int R, bool cyclic, bool per_row_any,
                         const std::function<double(int, int)> &coef, int M_req, SegPlan &sp,
                         std::string &msg, int L_req = 0, int pref = PREF_S, int m_max = 16, int interior = 0,
@@ -953,6 +1027,8 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       p.LtUtg[((size_t)i * 2 + 0) * R * R + q] = B.Lt[i][q];
       p.LtUtg[((size_t)i * 2 + 1) * R * R + q] = B.Ut[i][q];
     }
+  s = boundary_rows(P, R, p.wg_start, line_coef, p.Kw, p.bfun, msg);
+  if (s != CB_OK) return s;
   return wg_program(B, p.prog, msg);
 }
 

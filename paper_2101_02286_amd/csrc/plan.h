@@ -105,6 +105,12 @@ struct Plan {
   std::vector<double> SRg;             // per partition: S^G [N_i][R] then R^G [N_i][R]
   std::vector<int64_t> SRg_off;        // P
   std::vector<double> LtUtg;           // [P][2][R][R]
+  // rows 0..R-1 and N_i-R..N_i-1 of D_i^{-1} over windows of Kw rows at the
+  // ends of D_i (entries beyond the window are below 2^-56 of the row's
+  // absolute sum): [P][2][R][Kw], first-end window rows 0..Kw-1, last-end
+  // window rows N_i-Kw..N_i-1
+  int Kw = 0;
+  std::vector<double> bfun;
   RedProgram prog;
   // device buffers
   void *dev_base = nullptr;
@@ -117,6 +123,7 @@ struct Plan {
   const double *d_LtUtg = nullptr;
   const int *d_row_off = nullptr, *d_src = nullptr;
   const double *d_mats = nullptr;
+  const double *d_bfun = nullptr;
   const double *d_bands = nullptr;     // n*(2r+1) per-row bands
   // long FP64 lines (n > 4096) of a one-partition plan: strided launches run
   // the same matrix split into workgroup partitions of about 1024 rows, since

@@ -116,6 +116,22 @@ def solve_segment(plan, b, seg=0):
     return x
 
 
+def boundary_values(plan, b):
+    """First and last R rows of y_i = D_i^{-1} b_i for every partition, as
+    dot products of b_i's end windows with the plan's boundary rows."""
+    info = plan.info()
+    P, R, K = info["partitions"], info["r"], info["boundary_window"]
+    ws = plan.array(7).astype(int)
+    bf = plan.array(12).reshape(P, 2, R, K)
+    yf, yl = [], []
+    for i in range(P):
+        seg = b[:, ws[i] + R:ws[i + 1]]
+        N = seg.shape[1]
+        yf.append(seg[:, :K] @ bf[i, 0].T)
+        yl.append(seg[:, N - K:] @ bf[i, 1].T)
+    return yf, yl
+
+
 def solve(plan, b, seg=0):
     """x = A^{-1} b for (lines, n) b, following the plan's decomposition
     (seg = 1 selects the strided-launch lane layout of a one-partition plan)."""
@@ -135,10 +151,13 @@ def solve(plan, b, seg=0):
         Ni = ws[i + 1] - ws[i] - R
         sr.append((SR[off:off + Ni * R].reshape(Ni, R), SR[off + Ni * R:off + 2 * Ni * R].reshape(Ni, R)))
         off += 2 * Ni * R
+    # phase A: the first and last R rows of y_i from the plan's boundary
+    # rows of D_i^{-1} over their windows
+    yf, yl = boundary_values(plan, b)
     xr = np.zeros((P, nl, R))
     for i in range(P):
         ip = (i - 1) % P
-        xr[i] = b[:, ws[i]:ws[i] + R] - ys[ip][:, -R:] @ LtUt[i, 0].T - ys[i][:, :R] @ LtUt[i, 1].T
+        xr[i] = b[:, ws[i]:ws[i] + R] - yl[ip] @ LtUt[i, 0].T - yf[i] @ LtUt[i, 1].T
     row_off = plan.array(8).astype(int)
     src = plan.array(9).astype(int)
     mats = plan.array(10).reshape(-1, R, R)

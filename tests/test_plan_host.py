@@ -80,6 +80,45 @@ def test_partitioned_plan_reproduces_oracle(P, name, cyclic):
     assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("P,n", [(3, 3 * 40), (4, 4 * 512 + 5), (16, 8192)])
+@pytest.mark.parametrize("name", ["tri", "penta"])
+@pytest.mark.parametrize("cyclic", [True, False])
+def test_boundary_rows_of_interior_inverse(P, n, name, cyclic):
+    """Phase A's functionals: the first and last r rows of y_i = D_i^{-1} b_i
+    from the plan's windowed boundary rows equal those of a dense solve of
+    each interior block D_i (numpy), for random b."""
+    bands = np.asarray(_bands(name))
+    r = (len(bands) - 1) // 2
+    p = cb.Plan(bands, n, partitions=P, cyclic=cyclic, host_only=True)
+    K = p.info()["boundary_window"]
+    ws = p.array(7).astype(int)
+    assert 0 < K <= min(np.diff(ws)) - r
+    b = np.random.default_rng(n + P).standard_normal((3, n))
+    yf, yl = plan_emulator.boundary_values(p, b)
+    for i in range(P):
+        d0, d1 = ws[i] + r, ws[i + 1]
+        N = d1 - d0
+        D = np.zeros((N, N))
+        for j in range(N):
+            for o in range(-r, r + 1):
+                if 0 <= j + o < N:
+                    D[j, j + o] = bands[o + r]
+        y = np.linalg.solve(D, b[:, d0:d1].T).T
+        scale = np.abs(y).max()
+        assert np.abs(yf[i] - y[:, :r]).max() <= 1e-14 * scale
+        assert np.abs(yl[i] - y[:, N - r:]).max() <= 1e-14 * scale
+
+
+def test_boundary_window_is_short_for_compact_schemes():
+    """The kept windows of the compact schemes' boundary rows (entries omitted
+    below 2^-56 of the row's absolute sum): about 41 rows for alpha = 1/3, 68
+    for the tenth-order pentadiagonal scheme, independent of the block size."""
+    for name, lo, hi in (("tri", 35, 48), ("penta", 60, 76)):
+        for n in (16 * 512, 16 * 2048):
+            K = cb.Plan(_bands(name), n, partitions=16, host_only=True).info()["boundary_window"]
+            assert lo <= K <= hi, (name, n, K)
+
+
 def test_step_counts_match_paper():
     """Sec. 4: floor(log2 p) block-PCR steps; popcount(p)-1 detach steps."""
     for P in range(2, 34):
