@@ -62,7 +62,9 @@ typedef struct cb_plan_s *cb_plan_t;
 
 /* The problem statement A x = b (Sec. 2-3). */
 typedef struct {
-  int32_t r;             /* half bandwidth: 1 tridiagonal, 2 pentadiagonal (1..2) */
+  int32_t r;             /* half bandwidth: 1 tridiagonal, 2 pentadiagonal, 3
+                            heptadiagonal (1..3; r = 3 takes rows_per_lane
+                            0, 8 or 16) */
   int32_t n;             /* system (line) length */
   const double *bands;   /* HOST.  per_row = 0: 2r+1 values a_{-r..r}, row j reads
                             A[j][j+o] = a_o.  per_row = 1: n*(2r+1) values,

@@ -20,6 +20,17 @@ DERIV6 = dict(alpha=Fr(1, 3), beta=Fr(0), a=Fr(14, 9), b=Fr(1, 9), c=Fr(0))
 # exactly in the tests.
 DERIV10 = dict(alpha=Fr(1, 2), beta=Fr(1, 20), a=Fr(17, 12), b=Fr(101, 150), c=Fr(1, 100))
 
+# Twelfth-order member with three left-hand neighbours (heptadiagonal, the
+# general band of Sec. 2 Eq. (4) with r = 3):
+# gamma f'_{j-3} + beta f'_{j-2} + alpha f'_{j-1} + f'_j + ... (symmetric)
+#   = a (f_{j+1}-f_{j-1})/(2h) + b (f_{j+2}-f_{j-2})/(4h) + c (f_{j+3}-f_{j-3})/(6h).
+# The six coefficients are the unique solution of the Taylor order
+# conditions through twelfth order (checked exactly in the tests); the
+# matrix is not diagonally dominant but its symbol stays positive (>= 1/20),
+# so it is symmetric positive definite.
+DERIV12H = dict(alpha=Fr(9, 16), beta=Fr(9, 100), gamma=Fr(1, 400), a=Fr(21, 16), b=Fr(231, 250),
+                c=Fr(147, 2000))
+
 # Sec. 1 Eq. (2) and App. A.2: collocated -> staggered interpolation,
 # alpha^ f^I_{j-1} + f^I_j + alpha^ f^I_{j+1} = a (f_{j+1/2}+f_{j-1/2})/2 + b (f_{j+3/2}+f_{j-3/2})/2
 INTERP6 = dict(alpha=Fr(3, 10), a=Fr(3, 2), b=Fr(1, 10))
@@ -30,10 +41,14 @@ STAG6 = dict(alpha=Fr(9, 62), a=Fr(63, 62), b=Fr(17, 62))
 
 
 def bands_collocated(s):
-    """LHS bands [beta, alpha, 1, alpha, beta] (r=2) or [alpha, 1, alpha] (r=1)."""
-    if s.get("beta", 0) != 0:
-        return [float(s["beta"]), float(s["alpha"]), 1.0, float(s["alpha"]), float(s["beta"])]
-    return [float(s["alpha"]), 1.0, float(s["alpha"])]
+    """LHS bands [gamma, beta, alpha, 1, alpha, beta, gamma] (r=3),
+    [beta, alpha, 1, alpha, beta] (r=2) or [alpha, 1, alpha] (r=1)."""
+    al, be, ga = float(s["alpha"]), float(s.get("beta", 0)), float(s.get("gamma", 0))
+    if ga != 0.0:
+        return [ga, be, al, 1.0, al, be, ga]
+    if be != 0.0:
+        return [be, al, 1.0, al, be]
+    return [al, 1.0, al]
 
 
 def stencil_deriv_collocated(s, h):

@@ -397,9 +397,12 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   int mode = (g.rs == 1) ? MODE_X : MODE_S;
   const int Q = st ? (st->lo >= -2 && st->hi <= 2 ? 2 : 3) : 0;  // stencil half-width of the kernel
   if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "more than 2^31 lines in one call");
-  const WgKernel *k = find_wg_kernel(p.R, p.M, mode, Q, p.segs[0].ilu != 0);
+  // the partitions' lane layout for this launch's row stride
+  const int so = mode == MODE_S ? p.seg_s : 0;
+  const int M = p.segs[so].M;
+  const WgKernel *k = find_wg_kernel(p.R, M, mode, Q, p.segs[so].ilu != 0);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
-  const int L = p.L;
+  const int L = p.segs[so].L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
   NT = std::min(std::max(NT, L), k->max_threads);
@@ -408,14 +411,14 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // the device's LDS per workgroup
   const int RSw = 2 * std::max(p.R, Q);
   size_t coef_doubles = 0;
-  for (const SegPlan &sp : p.segs) coef_doubles = std::max(coef_doubles, (size_t)sp.ntypes * sp.block);
+  for (int i = so; i < so + p.P; ++i) coef_doubles = std::max(coef_doubles, (size_t)p.segs[i].ntypes * p.segs[i].block);
   const bool coef_lds = coef_doubles * 8 <= 16384;
   const size_t extra = coef_lds ? coef_doubles : 0;
   // unit-stride lines are loaded and stored through an LDS tile of W lines
   const bool stage_x = mode == MODE_X && p.desc.x_staging != 1;
   int smax = 0;
-  for (const SegPlan &sp : p.segs) smax = std::max(smax, sp.S);
-  const int64_t pitch = stage_x ? smax + smax / p.M + 1 : 0;
+  for (int i = so; i < so + p.P; ++i) smax = std::max(smax, p.segs[i].S);
+  const int64_t pitch = stage_x ? smax + smax / M + 1 : 0;
   auto lds_c_of = [&](int nt) { return ((size_t)nt * 2 * RSw + extra + (size_t)(nt / L) * pitch) * 8; };
   // phase B: one thread per (line, partition), 256-thread blocks
   const int NTB = 256, WB = std::max(1, NTB / p.P);
@@ -448,7 +451,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.stage_off_a = a.coef_off_a + (int64_t)extra;
   a.stage_off_c = a.coef_off_c + (int64_t)extra;
   a.stage_pitch = pitch;
-  a.segs = p.segdev;
+  a.segs = p.segdev + so;
   a.wg_start = p.d_wg_start;
   a.bands = p.d_bands;
   a.SR = p.d_SRg;

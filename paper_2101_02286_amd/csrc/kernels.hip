@@ -265,9 +265,10 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
       double bf[CH], bl[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        const int j = j0 + u * T + t;
-        bf[u] = j < K ? rhs(j) : 0.0;
-        bl[u] = j < K ? rhs(N - K + j) : 0.0;
+        // a block one row shorter than the window has a zero weight there
+        const int j = j0 + u * T + t, jl = N - K + j;
+        bf[u] = (j < K && j < N) ? rhs(j) : 0.0;
+        bl[u] = (j < K && jl >= 0) ? rhs(jl) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -492,7 +493,11 @@ __global__ __launch_bounds__(256) void k_stencil(const StencilArgs a) {
 const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu) {
   int cnt = 0;
   const LineKernel *t = nullptr;
-  switch (M) {
+  if (R == 3) {
+    if (M == 8) t = line_table_r3_m8(&cnt);
+    else if (M == 16) t = line_table_r3_m16(&cnt);
+    else return nullptr;
+  } else switch (M) {
     case 4: t = line_table_m4(&cnt); break;
     case 6: t = line_table_m6(&cnt); break;
     case 8: t = line_table_m8(&cnt); break;
@@ -516,6 +521,7 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
 static const WgKernel kWgKernels[] = {
     CB_WG_Q(1, 8, MODE_X), CB_WG_Q(1, 8, MODE_S), CB_WG_Q(2, 8, MODE_X), CB_WG_Q(2, 8, MODE_S),
     CB_WG_Q(1, 16, MODE_X), CB_WG_Q(1, 16, MODE_S), CB_WG_Q(2, 16, MODE_X), CB_WG_Q(2, 16, MODE_S),
+    CB_WG_Q(3, 8, MODE_X),  CB_WG_Q(3, 8, MODE_S),  CB_WG_Q(3, 16, MODE_X), CB_WG_Q(3, 16, MODE_S),
 };
 
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu) {
@@ -529,7 +535,11 @@ const void *stencil_kernel() { return (const void *)&k_stencil; }
 const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q) {
   int cnt = 0;
   const BatchKernel *t = nullptr;
-  switch (M) {
+  if (R == 3) {
+    if (M == 8) t = batch_table_r3_m8(&cnt);
+    else if (M == 16) t = batch_table_r3_m16(&cnt);
+    else return nullptr;
+  } else switch (M) {
     case 4: t = batch_table_m4(&cnt); break;
     case 6: t = batch_table_m6(&cnt); break;
     case 8: t = batch_table_m8(&cnt); break;

@@ -41,7 +41,7 @@ struct LineArgs {
   int64_t stage_pitch;       // doubles per line in the tile (n + n/M + 1)
   SegDev seg;
   double stc[7];             // stencil coefficients for q = -3..3 (zero padded)
-  double bands[5];           // constant bands a_{-R..R} (refinement residual)
+  double bands[2 * kMaxR + 1];  // constant bands a_{-R..R} (refinement residual)
   const double *bands_row;   // per-row bands [n][2R+1] or nullptr
 };
 

@@ -376,5 +376,10 @@ const BatchKernel *batch_table_m8(int *count);
 const BatchKernel *batch_table_m12(int *count);
 const BatchKernel *batch_table_m16(int *count);
 const BatchKernel *batch_table_m32(int *count);
+// heptadiagonal (r = 3) instances (lines_r3_m<M>.hip)
+const LineKernel *line_table_r3_m8(int *count);
+const LineKernel *line_table_r3_m16(int *count);
+const BatchKernel *batch_table_r3_m8(int *count);
+const BatchKernel *batch_table_r3_m16(int *count);
 
 }  // namespace cb

@@ -84,7 +84,7 @@ bool inverse(const Mat &a, int R, Mat &out) {
   return true;
 }
 
-// Small dense solve (size <= 4), partial pivoting.
+// Small dense solve (size <= 2 * kMaxR), partial pivoting.
 bool small_solve(int m, double *a, double *x, double scale) {
   for (int k = 0; k < m; ++k) {
     int p = k;
@@ -157,7 +157,7 @@ cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR
       const int Qp = std::min(2 * R, (N - 1 - j) / s);  // rows below
       const int Em = (std::min(2 * R - 1, Qm) + 1) / 2;  // equations/unknowns above
       const int Ep = (std::min(2 * R - 1, Qp) + 1) / 2;
-      int qs[4], os[4];
+      int qs[2 * kMaxR], os[2 * kMaxR];
       int m = 0;
       for (int q = Em; q >= 1; --q) qs[m++] = -q;
       for (int q = 1; q <= Ep; ++q) qs[m++] = q;
@@ -169,7 +169,7 @@ cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR
       // can vanish entirely.  Such an equation is vacuous: the outer row it
       // pairs with (q = +-2) is then not needed and gets k = 0, exactly as at
       // the ends of D.  Remaining equations are scaled to unit row maximum.
-      bool vac[4] = {false, false, false, false}, drop[4] = {false, false, false, false};
+      bool vac[2 * kMaxR] = {}, drop[2 * kMaxR] = {};
       for (int r = 0; r < m; ++r) {
         double rmax = 0.0;
         for (int u = 0; u < m; ++u) rmax = std::max(rmax, std::fabs(at(j + qs[u] * s, os[r] - qs[u])));
@@ -180,7 +180,7 @@ cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR
             if (qs[u] == qd) drop[u] = true;
         }
       }
-      int qk[4], ok[4], mk = 0, ne = 0;
+      int qk[2 * kMaxR], ok[2 * kMaxR], mk = 0, ne = 0;
       for (int r = 0; r < m; ++r)
         if (!vac[r]) ok[ne++] = os[r];
       for (int u = 0; u < m; ++u)
@@ -189,7 +189,7 @@ cb_status gpcr_factor(int N, int R, const std::vector<double> &band, int T, GPCR
         msg = "generalized PCR reduction system is singular";
         return CB_ERR_SINGULAR;
       }
-      double a[16], x[4];
+      double a[4 * kMaxR * kMaxR], x[2 * kMaxR];
       for (int r = 0; r < mk; ++r) {
         double rmax = 0.0;
         for (int u = 0; u < mk; ++u) {
@@ -253,6 +253,49 @@ void gpcr_apply(const GPCR &g, double *y) {
   for (int j = 0; j < N; ++j) y[j] *= g.dinv[j];
 }
 
+// Banded LU without pivoting of one lane's interior block (unit lower L):
+// out[j*2R + q-1] = L[j][j-q], out[j*2R + R+q-1] = U[j][j+q] / U[j][j],
+// dinv[j] = 1 / U[j][j].
+cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, double *dinv, std::string &msg) {
+  const int W = 2 * R + 1;
+  std::vector<double> a(band);
+  double scale = 0.0;
+  for (double v : band) scale = std::max(scale, std::fabs(v));
+  for (int k = 0; k < N; ++k) {
+    const double piv = a[k * W + R];
+    if (!(std::fabs(piv) > 1e-13 * scale)) {
+      msg = "interior elimination met a zero pivot";
+      return CB_ERR_SINGULAR;
+    }
+    for (int i = k + 1; i <= std::min(N - 1, k + R); ++i) {
+      const double l = a[i * W + (k - i + R)] / piv;
+      a[i * W + (k - i + R)] = l;
+      for (int j = k + 1; j <= std::min(N - 1, k + R); ++j) a[i * W + (j - i + R)] -= l * a[k * W + (j - k + R)];
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    dinv[j] = 1.0 / a[j * W + R];
+    for (int q = 1; q <= R; ++q) {
+      out[j * 2 * R + q - 1] = j - q >= 0 ? a[j * W + (R - q)] : 0.0;
+      out[j * 2 * R + R + q - 1] = j + q < N ? a[j * W + (R + q)] * dinv[j] : 0.0;
+    }
+  }
+  return CB_OK;
+}
+
+// x = D^{-1} x for one column, from the factors lane_lu returns.
+void lu_apply(int N, int R, const double *lu, const double *dinv, double *x) {
+  for (int j = 1; j < N; ++j)
+    for (int q = 1; q <= R; ++q)
+      if (j - q >= 0) x[j] -= lu[(size_t)j * 2 * R + q - 1] * x[j - q];
+  for (int j = N - 1; j >= 0; --j) {
+    double acc = x[j] * dinv[j];
+    for (int q = 1; q <= R; ++q)
+      if (j + q < N) acc -= lu[(size_t)j * 2 * R + R + q - 1] * x[j + q];
+    x[j] = acc;
+  }
+}
+
 // ------------------------------------------------ partitioned blocks (Sec. 3) --
 // A run of S rows split into P parts; part i has rows [st[i], st[i+1]), its
 // first R rows are interface rows and the rest the interior block D_i.
@@ -313,19 +356,35 @@ cb_status build_blocks(int P, int R, const std::vector<int> &st, bool cyclic,
           B.Ut[i][a * R + (t - R)] = v;  // first R interior rows of part i
         }
       }
-    const int T = Tfix >= 0 ? Tfix : ceil_log2(N);
-    cb_status stt = gpcr_factor(N, R, band, T, B.D[i], msg);
-    if (stt != CB_OK) return stt;
+    // Lane partitions (Tfix >= 0) keep the generalized-PCR multipliers of D_i
+    // (Eq. (3)), which the kernels use.  Workgroup partitions need only
+    // S_i and R_i from D_i, which banded elimination gives as well (deep
+    // generalized-PCR levels of a slowly decaying inverse can meet
+    // near-singular reduction systems).
+    std::vector<double> lu, dv;
+    if (Tfix >= 0) {
+      cb_status stt = gpcr_factor(N, R, band, Tfix, B.D[i], msg);
+      if (stt != CB_OK) return stt;
+    } else {
+      lu.resize((size_t)N * 2 * R);
+      dv.resize(N);
+      cb_status stt = lane_lu(N, R, band, lu.data(), dv.data(), msg);
+      if (stt != CB_OK) return stt;
+    }
+    auto apply = [&](double *col) {
+      if (Tfix >= 0) gpcr_apply(B.D[i], col);
+      else lu_apply(N, R, lu.data(), dv.data(), col);
+    };
     // S_i = D_i^{-1} L_i, R_i = D_i^{-1} U_i (Eqs. (15)-(16)), column by column
     B.Sm[i].assign((size_t)N * R, 0.0);
     B.Rm[i].assign((size_t)N * R, 0.0);
     std::vector<double> col(N);
     for (int c = 0; c < R; ++c) {
       for (int j = 0; j < N; ++j) col[j] = Lc[j * R + c];
-      gpcr_apply(B.D[i], col.data());
+      apply(col.data());
       for (int j = 0; j < N; ++j) B.Sm[i][j * R + c] = col[j];
       for (int j = 0; j < N; ++j) col[j] = Uc[j * R + c];
-      gpcr_apply(B.D[i], col.data());
+      apply(col.data());
       for (int j = 0; j < N; ++j) B.Rm[i][j * R + c] = col[j];
     }
   }
@@ -544,6 +603,10 @@ cb_status wg_program(const Blocks &B, RedProgram &pg, std::string &msg) {
 // workgroup, and fewer block-PCR levels in LDS).
 enum { PREF_X = 0, PREF_S = 1 };
 
+// Rows per lane that have kernel instances for each half bandwidth:
+// r = 1, 2: 4, 6, 8, 12, 16, 32; r = 3: 8 and 16.
+bool rows_per_lane_built(int R, int M) { return R <= 2 || M == 8 || M == 16; }
+
 bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_uni,
                  bool allow_uniform, int L_req = 0, int pref = PREF_S, int m_max = 16, int lcap = 1024) {
   static const int kUniMx[] = {8, 4, 6, 12, 16, 32};
@@ -558,6 +621,7 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
         if (M_req && m != M_req) continue;
         if (!M_req && m > m_max) continue;
         if (m < 2 * R || S % m) continue;
+        if (!rows_per_lane_built(R, m)) continue;
         const int l = S / m;
         const int lmax = pass == 0 ? 64 : lcap;
         if (!is_pow2(l) || l > lmax) continue;
@@ -578,45 +642,25 @@ bool lane_layout(int S, int R, int M_req, int &L, int &M, bool &uniform, int &m_
   else if (pref == PREF_S) M = m_max >= 16 ? 16 : 8;
   else M = ((S + 7) / 8 <= 512 || m_max < 16) ? 8 : 16;
   if (M != 8 && M != 16) return false;
-  if (L_req > 0) {
-    L = L_req;
-  } else {
-    L = 1;
-    while (L * M < S) L *= 2;
-    while (L > 1 && S / L < 2 * R) L /= 2;
-  }
-  if (L > lcap || (S + L - 1) / L > M || S / L < 2 * R) return false;
+  auto fits = [&](int m, int &l) {
+    if (L_req > 0) {
+      l = L_req;
+    } else {
+      l = 1;
+      while (l * m < S) l *= 2;
+      while (l > 1 && S / l < 2 * R) l /= 2;
+    }
+    return !(l > lcap || (S + l - 1) / l > m || S / l < 2 * R);
+  };
+  if (fits(M, L)) return true;
+  // lanes of 8 rows hold only 2r..8 of them: some lengths need 16-row lanes
+  // (r = 3 above all), the other way round when 16-row lanes exceed lcap
+  if (M_req || (M == 16 && m_max < 16)) return false;
+  const int alt = M == 8 ? 16 : 8;
+  if (alt == 16 && m_max < 16) return false;
+  if (!fits(alt, L)) return false;
+  M = alt;
   return true;
-}
-
-// Banded LU without pivoting of one lane's interior block (unit lower L):
-// out[j*2R + q-1] = L[j][j-q], out[j*2R + R+q-1] = U[j][j+q] / U[j][j],
-// dinv[j] = 1 / U[j][j].
-cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, double *dinv, std::string &msg) {
-  const int W = 2 * R + 1;
-  std::vector<double> a(band);
-  double scale = 0.0;
-  for (double v : band) scale = std::max(scale, std::fabs(v));
-  for (int k = 0; k < N; ++k) {
-    const double piv = a[k * W + R];
-    if (!(std::fabs(piv) > 1e-13 * scale)) {
-      msg = "interior elimination met a zero pivot";
-      return CB_ERR_SINGULAR;
-    }
-    for (int i = k + 1; i <= std::min(N - 1, k + R); ++i) {
-      const double l = a[i * W + (k - i + R)] / piv;
-      a[i * W + (k - i + R)] = l;
-      for (int j = k + 1; j <= std::min(N - 1, k + R); ++j) a[i * W + (j - i + R)] -= l * a[k * W + (j - k + R)];
-    }
-  }
-  for (int j = 0; j < N; ++j) {
-    dinv[j] = 1.0 / a[j * W + R];
-    for (int q = 1; q <= R; ++q) {
-      out[j * 2 * R + q - 1] = j - q >= 0 ? a[j * W + (R - q)] : 0.0;
-      out[j * 2 * R + R + q - 1] = j + q < N ? a[j * W + (R + q)] * dinv[j] : 0.0;
-    }
-  }
-  return CB_OK;
 }
 
 // --------------------------------------- boundary rows of D_i^{-1} (Sec. 4) --
@@ -629,16 +673,16 @@ cb_status lane_lu(int N, int R, const std::vector<double> &band, double *out, do
 // over a window at its own end of D_i: the window is the shortest one whose
 // omitted entries sum, in absolute value, to at most 2^-56 of the row's
 // absolute sum (below the rounding of the dot product itself).  One window
-// length Kw serves every partition and row; Kw <= min N_i.
+// length Kw serves every partition and row; Kw <= max N_i.
 cb_status boundary_rows(int P, int R, const std::vector<int> &st, const std::function<double(int, int)> &coef,
                         int &Kw, std::vector<double> &out, std::string &msg) {
   const int W = 2 * R + 1;
   const double rel = std::ldexp(1.0, -56);
   std::vector<std::vector<double>> rows((size_t)P * 2 * R);
-  int kmax = 1, nmin = 1 << 30;
+  int kmax = 1, nmax = 0;
   for (int i = 0; i < P; ++i) {
     const int s0 = st[i] + R, N = st[i + 1] - s0;
-    nmin = std::min(nmin, N);
+    nmax = std::max(nmax, N);
     // band of D_i^T: D^T[j][j+o] = D[j+o][j]
     std::vector<double> bt((size_t)N * W, 0.0);
     for (int j = 0; j < N; ++j)
@@ -679,7 +723,9 @@ cb_status boundary_rows(int P, int R, const std::vector<int> &st, const std::fun
         rows[((size_t)i * 2 + end) * R + a] = std::move(g);
       }
   }
-  Kw = std::min(kmax, nmin);
+  // a block shorter than the window (partitions differ by a row) keeps all
+  // its entries; the window positions beyond it hold zeros
+  Kw = std::min(kmax, nmax);
   out.assign((size_t)P * 2 * R * Kw, 0.0);
   for (int i = 0; i < P; ++i) {
     const int N = st[i + 1] - st[i] - R;
@@ -687,7 +733,10 @@ cb_status boundary_rows(int P, int R, const std::vector<int> &st, const std::fun
       for (int a = 0; a < R; ++a) {
         const std::vector<double> &g = rows[((size_t)i * 2 + end) * R + a];
         double *o = out.data() + (((size_t)i * 2 + end) * R + a) * Kw;
-        for (int j = 0; j < Kw; ++j) o[j] = g[end == 0 ? j : N - Kw + j];
+        for (int j = 0; j < Kw; ++j) {
+          const int row = end == 0 ? j : N - Kw + j;
+          o[j] = (row >= 0 && row < N) ? g[row] : 0.0;
+        }
       }
   }
   return CB_OK;
@@ -845,9 +894,13 @@ int auto_refine_iters(const cb_plan_desc &d) {
 }
 
 cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
-  if (d.r < 1 || d.r > 2) {
-    msg = "r must be 1 (tridiagonal) or 2 (pentadiagonal)";
-    return d.r > 2 ? CB_ERR_UNSUPPORTED : CB_ERR_INVALID_ARG;
+  if (d.r < 1 || d.r > kMaxR) {
+    msg = "r must be 1 (tridiagonal), 2 (pentadiagonal) or 3 (heptadiagonal)";
+    return d.r > kMaxR ? CB_ERR_UNSUPPORTED : CB_ERR_INVALID_ARG;
+  }
+  if (d.r == 3 && d.rows_per_lane && d.rows_per_lane != 8 && d.rows_per_lane != 16) {
+    msg = "heptadiagonal plans (r = 3) take 8 or 16 rows per lane";
+    return CB_ERR_UNSUPPORTED;
   }
   if (!d.bands) {
     msg = "bands is NULL";
@@ -921,7 +974,9 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     // per lane unless asked for
     // FP32 line kernels run at most 512 threads, so at most 512 lanes: long
     // FP32 lines may use 16 rows per lane
-    const int m_max = d.precision == CB_FP64 || n > 8 * 512 ? 16 : 8;
+    // (r = 3: lanes of 8 rows fit only lines of 6..8 rows per lane, so FP32
+    // may take 16 there too)
+    const int m_max = d.precision == CB_FP64 || n > 8 * 512 || R == 3 ? 16 : 8;
     const int lcap = d.precision == CB_FP64 ? 1024 : 512;
     p.segs.resize(1);
     // unit-stride lines: generalized PCR interiors on uniform FP64 lanes,
@@ -980,40 +1035,60 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
   Blocks B;
   cb_status s = build_blocks(P, R, p.wg_start, cyclic, line_coef, -1, B, msg);
   if (s != CB_OK) return s;
-  // one lane layout for all partitions (the kernel has one M)
-  int M = d.rows_per_lane, Lg = 0;
-  {
+  // One lane layout per set of partitions (a kernel has one M): segs[0..P)
+  // for unit-stride launches, 8 rows per lane while a partition needs at most
+  // 64 lanes of them, else 16; strided launches take 16 rows per lane in
+  // segs[P..2P) (measured faster at every P: n = 8192, P = 16: 209 vs 150
+  // GDOF/s along y), or the unit-stride set when that already has 16.
+  auto build_set = [&](int M, std::vector<SegPlan> &set) -> cb_status {
     const int Smax = base + (extra ? 1 : 0) - R;
-    if (!M) M = (Smax + 7) / 8 <= 64 ? 8 : 16;  // at most 64 lanes of 8 rows, else 16 rows
-    int m_uni;
+    int Lg = 0, m_uni;
     bool uni;
     if (!lane_layout(Smax, R, M, Lg, M, uni, m_uni, false)) {
       msg = "no lane layout for the partition size";
       return CB_ERR_UNSUPPORTED;
     }
-  }
-  p.segs.resize(P);
-  for (int pass = 0; pass < 2; ++pass) {
-    // one kernel serves all partitions: every segment takes the same interior
-    // solve (elimination for all, or generalized PCR for all)
-    const int interior = d.interior ? d.interior : (pass == 0 ? 2 : 1);
-    s = CB_OK;
-    for (int i = 0; i < P && s == CB_OK; ++i) {
-      const int g0 = p.wg_start[i] + R;
-      const int S = p.wg_start[i + 1] - g0;
-      auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
-      s = build_segment(S, R, false, true, seg_coef, M, p.segs[i], msg, Lg, PREF_S, 16, interior);
+    set.assign(P, SegPlan());
+    cb_status st = CB_OK;
+    for (int pass = 0; pass < 2; ++pass) {
+      // one kernel serves all partitions: every segment takes the same
+      // interior solve (elimination for all, or generalized PCR for all)
+      const int interior = d.interior ? d.interior : (pass == 0 ? 2 : 1);
+      st = CB_OK;
+      for (int i = 0; i < P && st == CB_OK; ++i) {
+        const int g0 = p.wg_start[i] + R;
+        const int S = p.wg_start[i + 1] - g0;
+        auto seg_coef = [&, g0](int g, int o) -> double { return line_coef(g0 + g, o); };
+        st = build_segment(S, R, false, true, seg_coef, M, set[i], msg, Lg, PREF_S, 16, interior);
+      }
+      if (st == CB_OK || d.interior) break;
     }
-    if (s == CB_OK || d.interior) break;
-  }
+    if (st != CB_OK) return st;
+    for (int i = 1; i < P; ++i)
+      if (set[i].L != set[0].L) {
+        msg = "partition sizes need different lane counts; choose n divisible by P";
+        return CB_ERR_UNSUPPORTED;
+      }
+    return CB_OK;
+  };
+  const int Smax0 = base + (extra ? 1 : 0) - R;
+  const int M = d.rows_per_lane ? d.rows_per_lane : ((Smax0 + 7) / 8 <= 64 ? 8 : 16);
+  s = build_set(M, p.segs);
+  if (s != CB_OK && !d.rows_per_lane && M == 8) s = build_set(16, p.segs);
   if (s != CB_OK) return s;
-  p.M = M;
+  p.M = p.segs[0].M;
   p.L = p.segs[0].L;
-  for (int i = 1; i < P; ++i)
-    if (p.segs[i].L != p.L) {
-      msg = "partition sizes need different lane counts; choose n divisible by P";
-      return CB_ERR_UNSUPPORTED;
+  p.seg_s = 0;
+  if (!d.rows_per_lane && p.M != 16) {
+    std::vector<SegPlan> strided;
+    std::string m2;
+    std::swap(m2, msg);
+    if (build_set(16, strided) == CB_OK) {
+      p.seg_s = P;
+      for (SegPlan &sp : strided) p.segs.push_back(std::move(sp));
     }
+    std::swap(m2, msg);  // a strided set that cannot be built leaves the unit-stride one for both
+  }
   p.SRg.clear();
   p.SRg_off.assign(P, 0);
   for (int i = 0; i < P; ++i) {

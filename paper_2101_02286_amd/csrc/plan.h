@@ -10,6 +10,9 @@
 
 namespace cb {
 
+// Widest band the library handles: half bandwidth r <= kMaxR (w = 2r+1 <= 7).
+constexpr int kMaxR = 3;
+
 // ---------------------------------------------------------------------------
 // Lane-level plan of one "segment": a run of S consecutive rows of a line that
 // one workgroup solves (the whole line when the line has one partition, else

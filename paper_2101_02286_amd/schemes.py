@@ -19,22 +19,30 @@ not a step of the solve.
            values at x_j
   stag6    sixth-order staggered first derivative, App. A.2: bands
            [9/62, 1, 9/62], a = 63/62, b = 17/62; "c2s" and "s2c" as above
+  hept12   twelfth-order collocated first derivative with a heptadiagonal
+           left-hand side (Sec. 2's general band, r = 3): bands
+           [1/400, 9/100, 9/16, 1, 9/16, 9/100, 1/400], a = 21/16,
+           b = 231/250, c = 147/2000 (the Taylor order conditions through
+           twelfth order; symmetric positive definite, not diagonally dominant)
 """
 import math
 
 _SCHEMES = {
-    # name: (alpha, beta, a, b, c)
-    "tri6": (1.0 / 3.0, 0.0, 14.0 / 9.0, 1.0 / 9.0, 0.0),
-    "penta10": (1.0 / 2.0, 1.0 / 20.0, 17.0 / 12.0, 101.0 / 150.0, 1.0 / 100.0),
-    "interp6": (3.0 / 10.0, 0.0, 3.0 / 2.0, 1.0 / 10.0, 0.0),
-    "stag6": (9.0 / 62.0, 0.0, 63.0 / 62.0, 17.0 / 62.0, 0.0),
+    # name: (alpha, beta, gamma, a, b, c)
+    "tri6": (1.0 / 3.0, 0.0, 0.0, 14.0 / 9.0, 1.0 / 9.0, 0.0),
+    "penta10": (1.0 / 2.0, 1.0 / 20.0, 0.0, 17.0 / 12.0, 101.0 / 150.0, 1.0 / 100.0),
+    "hept12": (9.0 / 16.0, 9.0 / 100.0, 1.0 / 400.0, 21.0 / 16.0, 231.0 / 250.0, 147.0 / 2000.0),
+    "interp6": (3.0 / 10.0, 0.0, 0.0, 3.0 / 2.0, 1.0 / 10.0, 0.0),
+    "stag6": (9.0 / 62.0, 0.0, 0.0, 63.0 / 62.0, 17.0 / 62.0, 0.0),
 }
-DERIVATIVES = ("tri6", "penta10")
+DERIVATIVES = ("tri6", "penta10", "hept12")
 
 
 def bands(name):
     """Constant bands a_{-r..r} of the scheme's left-hand side."""
-    al, be = _SCHEMES[name][:2]
+    al, be, ga = _SCHEMES[name][:3]
+    if ga:
+        return [ga, be, al, 1.0, al, be, ga]
     return [be, al, 1.0, al, be] if be else [al, 1.0, al]
 
 
@@ -46,7 +54,7 @@ def stencil(name, n, grid="c2s"):
     """(lo, coefs) of the scheme's periodic right-hand side for lines of n points.
 
     Collocated derivatives (tri6, penta10) ignore `grid`."""
-    al, be, a, b, c = _SCHEMES[name]
+    al, be, ga, a, b, c = _SCHEMES[name]
     h = spacing(n)
     if name in DERIVATIVES:
         if c:

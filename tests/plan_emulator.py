@@ -127,8 +127,14 @@ def boundary_values(plan, b):
     for i in range(P):
         seg = b[:, ws[i] + R:ws[i + 1]]
         N = seg.shape[1]
-        yf.append(seg[:, :K] @ bf[i, 0].T)
-        yl.append(seg[:, N - K:] @ bf[i, 1].T)
+        # window rows 0..K-1 and N-K..N-1; rows outside the block (a block
+        # shorter than the window) have zero weights
+        first = np.zeros((b.shape[0], K))
+        last = np.zeros((b.shape[0], K))
+        first[:, :min(K, N)] = seg[:, :min(K, N)]
+        last[:, max(0, K - N):] = seg[:, max(0, N - K):]
+        yf.append(first @ bf[i, 0].T)
+        yl.append(last @ bf[i, 1].T)
     return yf, yl
 
 

@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 TRI = schemes.bands_collocated(schemes.DERIV6)
 PENTA = schemes.bands_collocated(schemes.DERIV10)
+HEPT = schemes.bands_collocated(schemes.DERIV12H)
 
 
 def relerr(x, ref):
@@ -22,7 +23,7 @@ def relerr(x, ref):
 
 
 def stencil_for(scheme, n):
-    s = schemes.DERIV6 if scheme == "tri6" else schemes.DERIV10
+    s = dict(tri6=schemes.DERIV6, penta10=schemes.DERIV10, hept12=schemes.DERIV12H)[scheme]
     lo, c = schemes.stencil_deriv_collocated(s, 2 * math.pi / n)
     return lo, c
 
@@ -103,6 +104,9 @@ def test_mixed_plans_one_batch(gpu):
         # acyclic items with the same bands on every row (FP64 and FP32 + refinement)
         (TRI, 300, "fp32_refine", 0, False, 1, False, False), (PENTA, 512, "fp32_refine", 2, False, 0, False, False),
         (TRI, 96, "fp64", 0, False, 2, False, False),
+        # heptadiagonal (r = 3) items: fused, FP32 + refinement, acyclic
+        (HEPT, 256, "fp64", 0, False, 0, True, True), (HEPT, 300, "fp32_refine", 0, False, 2, False, True),
+        (HEPT, 613, "fp64", 0, False, 1, False, False),
     ]
     items, singles, refs = [], [], []
     rng = np.random.default_rng(5)
@@ -119,7 +123,7 @@ def test_mixed_plans_one_batch(gpu):
             plan = cb.Plan(bands, n, precision=prec, refine_iters=it, cyclic=cyclic)
         if fused:
             f, _ = synth.random_modes(shape, seed=k)
-            lo, c = stencil_for("tri6" if bands is TRI else "penta10", n)
+            lo, c = stencil_for("tri6" if bands is TRI else ("penta10" if bands is PENTA else "hept12"), n)
             st = cb.Stencil(lo, c)
             refs.append(oracle.apply_axis(f.numpy(), axis, bands, lo, c))
             fd = f.to(gpu)

@@ -192,6 +192,65 @@ def test_long_ragged_unit_stride_lines(gpu, n):
     assert relerr(out, oracle.apply_axis(f.numpy(), 0, TRI, lo, c)) <= 1e-12
 
 
+HEPT = schemes.bands_collocated(schemes.DERIV12H)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [7, 96, 256, 300, 613])
+@pytest.mark.parametrize("cyclic", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_heptadiagonal_solve(gpu, axis, n, cyclic, prec):
+    """r = 3 (the general band of Sec. 2 Eq. (4)): the twelfth-order scheme's
+    heptadiagonal matrix along every axis, uniform (96, 256) and ragged lines,
+    cyclic and acyclic, FP64 and FP32 + refinement (automatic count)."""
+    b = synth.random_uniform(shape_with(axis, n, (6, 10)), seed=n + 3 * axis + cyclic)
+    plan = cb.Plan(HEPT, n, cyclic=cyclic, precision=prec)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    ref = oracle.solve_axis(b.numpy(), axis, HEPT, cyclic=cyclic)
+    assert relerr(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [64, 512, 613])
+def test_heptadiagonal_fused_derivative(gpu, axis, n):
+    """Twelfth-order compact derivative (7-point stencil fused with the
+    heptadiagonal solve) against the oracle."""
+    f, _ = synth.random_modes(shape_with(axis, n, (5, 6)), seed=n + axis)
+    lo, c = deriv_stencil(schemes.DERIV12H, n)
+    plan = cb.Plan(HEPT, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    ref = oracle.apply_axis(f.numpy(), axis, HEPT, lo, c)
+    assert relerr(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("cyclic", [True, False])
+def test_heptadiagonal_partitioned(gpu, P, axis, cyclic):
+    """r = 3 lines split over P workgroup partitions (solve), and the fused
+    derivative on the cyclic ones."""
+    n = 128 * P + 5
+    b = synth.random_uniform(shape_with(axis, n, (5, 6)), seed=P + axis)
+    plan = cb.Plan(HEPT, n, partitions=P, cyclic=cyclic)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    assert relerr(x, oracle.solve_axis(b.numpy(), axis, HEPT, cyclic=cyclic)) <= 1e-12
+    if cyclic:
+        f, _ = synth.random_modes(shape_with(axis, n, (5, 6)), seed=P)
+        lo, c = deriv_stencil(schemes.DERIV12H, n)
+        out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+        assert relerr(out, oracle.apply_axis(f.numpy(), axis, HEPT, lo, c)) <= 1e-12
+
+
+def test_heptadiagonal_long_lines(gpu):
+    """n = 8192 heptadiagonal lines: unit-stride whole, strided in workgroup partitions."""
+    n = 8192
+    plan = cb.Plan(HEPT, n)
+    for axis in (0, 2):
+        b = synth.random_uniform(shape_with(axis, n, (3, 4)), seed=axis)
+        x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        assert relerr(x, oracle.solve_axis(b.numpy(), axis, HEPT)) <= 1e-12, axis
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192

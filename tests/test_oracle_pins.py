@@ -163,9 +163,9 @@ def test_matvec_acyclic_per_row_vs_dense():
 # ----------------------------------------------------- closed forms (Eq. 1, 2)
 def modified_wavenumber(s, kh):
     a, b, c = float(s["a"]), float(s["b"]), float(s.get("c", 0))
-    al, be = float(s["alpha"]), float(s.get("beta", 0))
+    al, be, ga = float(s["alpha"]), float(s.get("beta", 0)), float(s.get("gamma", 0))
     return (a * np.sin(kh) + b / 2 * np.sin(2 * kh) + c / 3 * np.sin(3 * kh)) / (
-        1 + 2 * al * np.cos(kh) + 2 * be * np.cos(2 * kh))
+        1 + 2 * al * np.cos(kh) + 2 * be * np.cos(2 * kh) + 2 * ga * np.cos(3 * kh))
 
 
 def modal_derivative(shape, modes, axis, s):
@@ -184,9 +184,9 @@ def modal_derivative(shape, modes, axis, s):
     return out
 
 
-@pytest.mark.parametrize("name", ["deriv6", "deriv10"])
+@pytest.mark.parametrize("name", ["deriv6", "deriv10", "deriv12h"])
 def test_derivative_closed_form(name):
-    s = dict(deriv6=schemes.DERIV6, deriv10=schemes.DERIV10)[name]
+    s = dict(deriv6=schemes.DERIV6, deriv10=schemes.DERIV10, deriv12h=schemes.DERIV12H)[name]
     shape = (24, 40, 32)
     f, modes = synth.random_modes(shape, seed=11)
     f = f.numpy()
@@ -202,15 +202,16 @@ def test_derivative_closed_form(name):
 def test_derivative_converges_at_design_order():
     """A single mode: error of the compact derivative vs the exact derivative
     falls as h^6 (sixth order) and h^10 (tenth order)."""
-    for s, order in ((schemes.DERIV6, 6), (schemes.DERIV10, 10)):
+    for s, order, ns in ((schemes.DERIV6, 6, (16, 32)), (schemes.DERIV10, 10, (16, 32)),
+                         (schemes.DERIV12H, 12, (20, 32))):
         errs = []
-        for n in (16, 32):
+        for n in ns:
             x = np.arange(n) * 2 * np.pi / n
             f = np.sin(3 * x)[None, None, :]
             lo, c = schemes.stencil_deriv_collocated(s, 2 * np.pi / n)
             d = oracle.apply_axis(f, 0, schemes.bands_collocated(s), lo, c)[0, 0]
             errs.append(np.abs(d - 3 * np.cos(3 * x)).max())
-        rate = math.log2(errs[0] / errs[1])
+        rate = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
         assert order - 0.5 < rate < order + 1.0, (order, rate)
 
 
@@ -266,6 +267,14 @@ def test_scheme_taylor_conditions_exact():
             assert a + 4 ** p * b + 9 ** p * c == (2 * p + 1) * (2 * al + 2 * 4 ** p * be), p
         p = P + 1  # and not one order more
         assert a + 4 ** p * b + 9 ** p * c != (2 * p + 1) * (2 * al + 2 * 4 ** p * be)
+    # heptadiagonal twelfth order: through p = 5, not p = 6
+    s = schemes.DERIV12H
+    a, b, c, al, be, ga = s["a"], s["b"], s["c"], s["alpha"], s["beta"], s["gamma"]
+    assert a + b + c == 1 + 2 * al + 2 * be + 2 * ga
+    for p in range(1, 7):
+        lhs = a + 4 ** p * b + 9 ** p * c
+        rhs = (2 * p + 1) * (2 * al + 2 * 4 ** p * be + 2 * 9 ** p * ga)
+        assert (lhs == rhs) == (p <= 5), p
     s = schemes.INTERP6
     assert s["a"] + s["b"] == 1 + 2 * s["alpha"]
     for p in (1, 2):

@@ -119,6 +119,49 @@ def test_boundary_window_is_short_for_compact_schemes():
             assert lo <= K <= hi, (name, n, K)
 
 
+HEPT = schemes.bands_collocated(schemes.DERIV12H)
+
+
+@pytest.mark.parametrize("n", [7, 13, 24, 37, 96, 256, 300, 613, 1024])
+@pytest.mark.parametrize("cyclic", [True, False])
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_heptadiagonal_plans_reproduce_oracle(n, cyclic, P, precision):
+    """r = 3 (Sec. 2's general band, Eq. (4)): the twelfth-order scheme's
+    heptadiagonal matrix, every lane layout the plan picks (unit-stride and
+    strided), one or several workgroup partitions."""
+    if P > 1 and (precision != "fp64" or n < 9 * P):
+        pytest.skip("partitioned plans are FP64 and need partitions of at least 3r rows")
+    p = cb.Plan(HEPT, n, cyclic=cyclic, partitions=P, precision=precision, host_only=True)
+    assert p.info()["r"] == 3
+    b = np.random.default_rng(n + P).standard_normal((3, n))
+    ref = oracle.solve_lines(b, HEPT, cyclic=cyclic)
+    segs = [0]
+    if P == 1 and p.info()["rows_per_lane_strided"] != p.info()["rows_per_lane"] or \
+            p.info()["interior_elimination_strided"] != p.info()["interior_elimination"]:
+        segs.append(1)
+    for seg in segs:
+        x = plan_emulator.solve(p, b, seg)
+        assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max(), seg
+
+
+def test_heptadiagonal_per_row_bands():
+    n, r = 200, 3
+    bands = synth.random_bands(n, r, seed=9)
+    for cyclic in (True, False):
+        p = cb.Plan(bands, n, per_row=True, cyclic=cyclic, host_only=True)
+        b = np.random.default_rng(1).standard_normal((2, n))
+        ref = oracle.solve_lines(b, bands, per_row=True, cyclic=cyclic)
+        assert np.abs(plan_emulator.solve(p, b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_heptadiagonal_rejects_unbuilt_lane_sizes():
+    with pytest.raises(cb.CbError):
+        cb.Plan(HEPT, 96, rows_per_lane=12, host_only=True)
+    with pytest.raises(cb.CbError):
+        cb.Plan([0.0] * 4 + [1.0] + [0.0] * 4, 96, host_only=True)  # r = 4
+
+
 def test_step_counts_match_paper():
     """Sec. 4: floor(log2 p) block-PCR steps; popcount(p)-1 detach steps."""
     for P in range(2, 34):
@@ -165,7 +208,7 @@ def test_singular_matrix_rejected():
 
 def test_bad_descriptors():
     with pytest.raises(cb.CbError) as e:
-        cb.Plan([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0], 64, host_only=True)
+        cb.Plan([1.0, 2.0, 3.0, 4.0, 9.0, 6.0, 7.0, 8.0, 9.0], 64, host_only=True)  # r = 4
     assert e.value.status == cb.CB_ERR_UNSUPPORTED
     with pytest.raises(cb.CbError):
         cb.Plan([1 / 3, 1, 1 / 3], 2, host_only=True)

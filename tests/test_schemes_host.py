@@ -19,7 +19,7 @@ def _close(a, b):
 @pytest.mark.parametrize("n", [32, 100, 256, 613, 8192])
 def test_derivative_schemes_match_pinned(n):
     h = 2 * math.pi / n
-    for name, s in (("tri6", osch.DERIV6), ("penta10", osch.DERIV10)):
+    for name, s in (("tri6", osch.DERIV6), ("penta10", osch.DERIV10), ("hept12", osch.DERIV12H)):
         assert _close(psch.bands(name), osch.bands_collocated(s)), name
         lo_p, c_p = psch.stencil(name, n)
         lo_o, c_o = osch.stencil_deriv_collocated(s, h)
