@@ -172,6 +172,13 @@ def headline(args):
     dom_ms = float(np.mean([per_dir_ms[ax] for ax in groups[dom]]))  # average launch duration
     achieved = BYTES_PER_DOF * dof / (dom_ms * 1e-3) / 1e9
     lat = dur.reshape(-1)
+    # the same launches with the arithmetic left out (cb_copy_lines): the
+    # ceiling of each direction's own access pattern
+    copy_ms = []
+    for ax in range(3):
+        copy_ms.append(_median_ms(lambda: cb.copy_lines(plans[ax], f, ax, out=outs[ax], stream=stream),
+                                  args.steps, args.warmup, stream))
+    dom_copy_ms = float(np.mean([copy_ms[ax] for ax in groups[dom]]))
     res = {
         "metric": "GDOF/s (solved unknowns per second), 512^3 cyclic tridiagonal compact derivative x/y/z",
         "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -190,10 +197,15 @@ def headline(args):
                                          for k, v in zip("xyz", per_dir_ms)},
         "solve_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                              "p99": round(float(np.percentile(lat, 99)), 4)},
+        "copy_same_pattern": {k: {"ms": round(c, 4), "gbs": round(BYTES_PER_DOF * dof / (c * 1e-3) / 1e9, 1),
+                                  "solve_over_copy_time": round(float(v) / c, 3)}
+                              for k, c, v in zip("xyz", copy_ms, per_dir_ms)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                      "kernel": "k_line %s (%s)" % (dom, ", ".join("xyz"[ax] for ax in groups[dom])),
-                     "avg_launch_ms": round(dom_ms, 4), "bytes_per_launch": BYTES_PER_DOF * dof},
+                     "avg_launch_ms": round(dom_ms, 4), "bytes_per_launch": BYTES_PER_DOF * dof,
+                     "copy_same_pattern_gbs": round(BYTES_PER_DOF * dof / (dom_copy_ms * 1e-3) / 1e9, 1),
+                     "frac_of_copy_same_pattern": round(dom_copy_ms / dom_ms, 4)},
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(f, bands, [st, st, st], seconds=args.cpu_seconds)

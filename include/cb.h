@@ -182,6 +182,16 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
 cb_status cb_solve_noalloc(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b,
                            double *x, void *stream);
 
+/* Diagnostic for the roofline: out = in along `axis`, moved exactly as
+ * cb_solve with this plan moves the data (the same workgroup tiles, lane
+ * layout, loads, LDS staging, stores and tile order) with the arithmetic
+ * left out, so its time is the ceiling of the solve's memory access pattern.
+ * One-partition launches only (CB_ERR_UNSUPPORTED for partitioned plans and
+ * for strided launches of long lines, which run in partitions).  in and out
+ * must not overlap. */
+cb_status cb_copy_lines(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *in, double *out,
+                        void *stream);
+
 /* One work item of a batched launch: a solve (stencil == NULL) or a fused
  * derivative along one axis of one grid. */
 typedef struct {

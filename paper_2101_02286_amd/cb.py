@@ -16,7 +16,7 @@ _lib = None
 CB_OK, CB_ERR_INVALID_ARG, CB_ERR_UNSUPPORTED, CB_ERR_SINGULAR, CB_ERR_OOM, CB_ERR_HIP = range(6)
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
 ABI_SYMBOLS = ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
-               "cb_solve_noalloc",
+               "cb_solve_noalloc", "cb_copy_lines",
                "cb_batch_workspace_size", "cb_batch_build", "cb_batch_launch", "cb_solve_batched",
                "cb_plan_get_info",
                "cb_plan_get_schedule", "cb_plan_get_array", "cb_last_error")
@@ -78,6 +78,7 @@ def lib():
         L.cb_rhs_stencil.argtypes = [ctypes.POINTER(StencilC), ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_solve.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_solve_noalloc.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, vp, vp]
+        L.cb_copy_lines.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_apply_derivative.argtypes = [vp, ctypes.POINTER(StencilC), ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_batch_workspace_size.argtypes = [i32]
         L.cb_batch_workspace_size.restype = ctypes.c_size_t
@@ -88,7 +89,8 @@ def lib():
         L.cb_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
         L.cb_plan_get_array.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(i64)]
         L.cb_last_error.restype = ctypes.c_char_p
-        for f in ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_solve_noalloc", "cb_apply_derivative",
+        for f in ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_solve_noalloc", "cb_copy_lines",
+                  "cb_apply_derivative",
                   "cb_solve_batched", "cb_batch_build", "cb_batch_launch", "cb_plan_get_info",
                   "cb_plan_get_schedule", "cb_plan_get_array"):
             getattr(L, f).restype = ctypes.c_int
@@ -216,6 +218,18 @@ def solve_noalloc(plan, b, axis, out, stream=None):
 
 
 NOALLOC_SCRATCH_BYTES = 32 << 20  # CB_NOALLOC_SCRATCH_BYTES
+
+
+def copy_lines(plan, f, axis, out=None, stream=None):
+    """cb_copy_lines: out = f moved with the plan's launch along `axis` and no
+    arithmetic (the access pattern's ceiling, for the roofline)."""
+    if out is None:
+        out = torch.empty_like(f)
+    g = grid_of(f)
+    if grid_of(out).stride[:] != g.stride[:]:
+        raise ValueError("f and out must have the same layout")
+    _check(lib().cb_copy_lines(plan.h, ctypes.byref(g), axis, _dev(f), _dev(out), _stream(stream)))
+    return out
 
 
 def apply_derivative(plan, stencil, f, axis, out=None, stream=None):

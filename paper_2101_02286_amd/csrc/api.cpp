@@ -280,10 +280,14 @@ void residual_bands(const Plan &p, LineArgs &a) {
 }
 
 // --------------------------------------------------------- P = 1 launch --
+// copy: the same launch with the copy-only kernel (no stencil, no solve).
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
-                      hipStream_t stream, const FixedScratch *fs) {
+                      hipStream_t stream, const FixedScratch *fs, bool copy = false) {
   // long strided lines: workgroup partitions of the same matrix
-  if (g.rs != 1 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
+  if (g.rs != 1 && p.strided_wg) {
+    if (copy) return fail(CB_ERR_UNSUPPORTED, "cb_copy_lines: this launch runs in workgroup partitions");
+    return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
+  }
   const int si = g.rs == 1 ? 0 : p.seg_s;  // lane layout for this launch's row stride
   const SegPlan &sp = p.segs[si];
   const bool uni = sp.uniform != 0;
@@ -303,11 +307,12 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
                     (g.nu == 1 || g.su % 2 == 0) && (g.nlines <= g.nu || g.sv % 2 == 0) && sp.M % 2 == 0;
     if (!al) mode = MODE_S;
   }
-  const LineKernel *lk = find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni, sp.ilu != 0);
+  const LineKernel *lk = copy ? find_copy_kernel(sp.M, mode, uni)
+                              : find_line_kernel(p.R, sp.M, fp32 ? 1 : 0, mode, Q, uni, sp.ilu != 0);
   if (!lk) return fail(CB_ERR_UNSUPPORTED, "no kernel instance for this plan layout");
   const void *fn = lk->fn;
   const int L = sp.L;
-  if (L > 1024 && p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
+  if (L > 1024 && p.strided_wg && !copy) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
   if (L > 1024) return fail(CB_ERR_UNSUPPORTED, "line needs more than 1024 lanes");
   int W;
   if (p.desc.lines_per_wg > 0) {
@@ -346,7 +351,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (lds_of(W) > cap || NT > lk->max_threads) {
     // a line longer than one workgroup of this kernel holds: the workgroup
     // partitions of the same matrix when the plan has them (FP64, n > 4096)
-    if (p.strided_wg) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
+    if (p.strided_wg && !copy) return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
     return fail(CB_ERR_UNSUPPORTED, "line too long for one workgroup of this kernel");
   }
   // lanes of a line are adjacent threads in MODE_X: with L <= 64 a line lies in
@@ -634,6 +639,20 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
     return launch_wg(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream), nullptr);
   }
   return launch_line(plan->p, g, f, out, stencil, static_cast<hipStream_t>(stream), nullptr);
+}
+
+cb_status cb_copy_lines(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *in, double *out,
+                        void *stream) {
+  cb_status s = check_plan_for_solve(plan);
+  if (s) return s;
+  Geo g;
+  if ((s = geometry(grid, axis, g))) return s;
+  if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
+  if (plan->p.P != 1) return fail(CB_ERR_UNSUPPORTED, "cb_copy_lines: one-partition plans only");
+  if (g.nlines == 0) return CB_OK;
+  if (!in || !out) return fail(CB_ERR_INVALID_ARG, "in and out must be non-NULL");
+  if (overlap(in, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "in and out overlap");
+  return launch_line(plan->p, g, in, out, nullptr, static_cast<hipStream_t>(stream), nullptr, true);
 }
 
 size_t cb_batch_workspace_size(int32_t n_items) {

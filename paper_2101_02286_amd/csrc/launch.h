@@ -128,6 +128,9 @@ cb_status solve_entry(cb_plan_t plan, const cb_grid *grid, int32_t axis, const d
 cb_status set_error(cb_status s, const char *msg);
 
 const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool uni, bool ilu);
+// copy-only instances (copy_lines.hip): the load and store path of each rows
+// per lane, row layout and lane layout
+const LineKernel *find_copy_kernel(int M, int mode, bool uni);
 const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q);
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu);
 const void *stencil_kernel();

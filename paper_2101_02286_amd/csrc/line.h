@@ -37,7 +37,9 @@ constexpr int line_region() {
 //         index cover W adjacent lines so each row access is one contiguous
 //         W*8-byte segment.
 // ------------------------------------------------------------------------
-template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU = false>
+// COPY: the same loads, tile and stores with the stencil and the solve left
+// out (x = b), the access pattern's own ceiling for the roofline.
+template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU = false, bool COPY = false>
 __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, double *smem) {
   constexpr int RS = line_region<R, Q, MODE>();
   LanePos p;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
     for (int k = 0; k < M; ++k) b64[k] = (active && (UNI || k < m)) ? __builtin_nontemporal_load(in + k * rs) : 0.0;
   }
 
-  if (Q > 0) {  // fused right-hand-side stencil (Eq. (1)/(2)), periodic
+  if (Q > 0 && !COPY) {  // fused right-hand-side stencil (Eq. (1)/(2)), periodic
     constexpr int QQ = Q > 0 ? Q : 1;
     double fp[QQ], fn[QQ];
     if (staged) {  // the neighbouring rows are in the LDS tile
@@ -174,7 +176,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
 
   // general layouts: the lanes read different coefficient blocks, staged in LDS
   T *cl = nullptr;
-  if (!UNI && a.coef_lds) {
+  if (!UNI && a.coef_lds && !COPY) {
     cl = reinterpret_cast<T *>(smem + (size_t)2 * RSr * blockDim.x);
     stage_coef<T>(sg, cl, p.tid, blockDim.x);
   }
@@ -186,7 +188,10 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   };
 
   double x64[M];
-  if (sizeof(T) == 8) {
+  if (COPY) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) x64[k] = b64[k];
+  } else if (sizeof(T) == 8) {
     T v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (T)b64[k];
@@ -264,7 +269,7 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   }
 }
 
-template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU>
+template <int R, int M, typename T, int MODE, int Q, bool UNI, bool ILU, bool COPY = false>
 __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_line(const LineArgs a) {
   extern __shared__ double smem[];
   uint32_t tile = blockIdx.x;
@@ -275,7 +280,7 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_li
     const uint32_t j = tile % X, s = tile / X;
     tile = j * q + (j < rem ? j : rem) + s;
   }
-  line_tile<R, M, T, MODE, Q, UNI, ILU>(a, (int64_t)tile, smem);
+  line_tile<R, M, T, MODE, Q, UNI, ILU, COPY>(a, (int64_t)tile, smem);
 }
 
 

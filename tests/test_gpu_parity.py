@@ -251,6 +251,25 @@ def test_heptadiagonal_long_lines(gpu):
         assert relerr(x, oracle.solve_axis(b.numpy(), axis, HEPT)) <= 1e-12, axis
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n,prec", [(512, "fp64"), (500, "fp64"), (613, "fp64"), (384, "fp32_refine"), (64, "fp64")])
+def test_copy_lines_moves_the_data_unchanged(gpu, axis, n, prec):
+    """cb_copy_lines (the solve's launch without arithmetic) writes every
+    element of the output with its input value, on every axis and layout."""
+    f = synth.random_uniform(shape_with(axis, n, (6, 40)), seed=n + axis).to(gpu)
+    plan = cb.Plan(TRI, n, precision=prec)
+    out = torch.full_like(f, float("nan"))
+    cb.copy_lines(plan, f, axis, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, f)
+    # strided launches of long one-partition lines run in partitions: refused
+    if axis > 0:
+        plan8 = cb.Plan(TRI, 8192)
+        g = torch.zeros(shape_with(axis, 8192, (4, 2)), dtype=torch.float64, device=gpu)
+        with pytest.raises(cb.CbError):
+            cb.copy_lines(plan8, g, axis, out=torch.empty_like(g))
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192
