@@ -146,8 +146,11 @@ cb_status cb_plan(const cb_plan_desc *desc, cb_plan_t *out);
  * using it is still pending.  NULL is accepted. */
 cb_status cb_plan_destroy(cb_plan_t plan);
 
-/* b = stencil(f) along `axis` (0 x, 1 y, 2 z), periodic wrap.  f and b are
- * device arrays laid out by `grid`; they must not overlap. */
+/* b = stencil(f) along `axis` (0 x, 1 y, 2 z), periodic wrap: the
+ * right-hand side of the compact derivative and interpolation (Sec. 1
+ * Eqs. (1)-(2); App. A.2 for the staggered forms).  f and b are device
+ * arrays laid out by `grid`; they must not overlap.  Errors: bad stencil,
+ * grid or axis, NULL or overlapping pointers (CB_ERR_INVALID_ARG). */
 cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t axis,
                          const double *f, double *b, void *stream);
 
@@ -158,8 +161,11 @@ cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const doub
                    double *x, void *stream);
 
 /* out = A^{-1} (stencil(f)) along `axis`: the compact derivative or
- * interpolation with the stencil fused into the solve (b never goes to
- * memory).  Requires a cyclic plan.  f and out must not overlap. */
+ * interpolation A f' = B f of Sec. 1 Eqs. (1)-(2) (App. A.2) with the
+ * stencil B fused into the solve of Sec. 4 (b never goes to memory).
+ * Requires a cyclic plan (the stencil is periodic).  f and out must not
+ * overlap.  Same errors as cb_solve, plus CB_ERR_INVALID_ARG for a bad
+ * stencil or an acyclic plan. */
 cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const cb_grid *grid,
                               int32_t axis, const double *f, double *out, void *stream);
 
