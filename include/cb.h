@@ -77,8 +77,12 @@ typedef struct {
                             P > 1 solves the reduced P-block system across
                             workgroups (any P, detach/reattach when P is not a
                             power of two).  0 = let the library choose: 1
-                            while a line fits one workgroup (n <= 16384),
-                            else, in FP64, ceil(n / 1024) up to 64. */
+                            while a line fits one workgroup (n <= 16384 in
+                            FP64, n <= 8192 in FP32), else ceil(n / 1024) up
+                            to 64.  FP32 + refinement with P > 1 refines
+                            across the partitions (each iteration runs the
+                            partitioned solve on the FP64 residual) and
+                            needs b and x apart. */
   int32_t precision;     /* cb_precision */
   int32_t refine_iters;  /* CB_FP32_REFINE: refinement iterations, 1..8, or 0:
                             automatic, the fewest k >= 1 with

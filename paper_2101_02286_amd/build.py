@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcb.so")
 SOURCES = ["kernels.hip", "lines_m4.hip", "lines_m6.hip", "lines_m8.hip", "lines_m12.hip", "lines_m16.hip",
-           "lines_m32.hip", "lines_r3_m8.hip", "lines_r3_m16.hip", "copy_lines.hip", "noalloc.hip",
+           "lines_m32.hip", "lines_r3_m8.hip", "lines_r3_m16.hip", "copy_lines.hip", "wg_fp32_m8.hip", "wg_fp32_m16.hip",
+           "noalloc.hip",
            "plan.cpp", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "--offload-arch=" + ARCH,

@@ -405,8 +405,11 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // the partitions' lane layout for this launch's row stride
   const int so = mode == MODE_S ? p.seg_s : 0;
   const int M = p.segs[so].M;
-  const WgKernel *k = find_wg_kernel(p.R, M, mode, Q, p.segs[so].ilu != 0);
+  const bool fp32 = p.precision != CB_FP64;
+  const WgKernel *k = fp32 ? find_wg32_kernel(p.R, M, mode, Q, p.segs[so].ilu != 0)
+                           : find_wg_kernel(p.R, M, mode, Q, p.segs[so].ilu != 0);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
+  const int iters = fp32 ? p.refine_iters : 0;  // refinement iterations after the first solve
   const int L = p.segs[so].L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
@@ -467,12 +470,21 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.mats = p.d_mats;
   a.bfun = p.d_bfun;
   a.kw = p.Kw;
+  // scratch per (line, partition): b~, the two ends of y, and when refining
+  // the current x at the interface rows
+  a.sc_stride = (iters > 0 ? 4 : 3) * p.R;
+  {
+    const int W2 = 2 * p.R + 1;
+    const size_t mid = (size_t)(p.n / 2) * W2;  // an interior row: every entry present
+    for (int o = 0; o < W2; ++o) a.band_c[o] = p.bands[mid + o];
+    a.band_rows = (p.desc.per_row || !p.desc.cyclic) ? 1 : 0;
+  }
   a.wave_local = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 1 : 0;
   // phase A: 256 threads; a unit-stride line per wavefront (consecutive rows
   // in consecutive lanes), strided lines 64 adjacent ones per row access
   constexpr int kNTA = 256;
   const int WA = mode == MODE_X ? kNTA / 64 : 64;
-  const size_t sbytes = (size_t)g.nlines * p.P * 3 * p.R * sizeof(double);
+  const size_t sbytes = (size_t)g.nlines * p.P * a.sc_stride * sizeof(double);
   void *scratch = nullptr;
   hipError_t e = hipSuccess;
   if (fs) {
@@ -495,10 +507,17 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   void *args[] = {&a};
   const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
   const size_t lds_c = ((size_t)a.stage_off_c + (size_t)W * pitch) * sizeof(double);
-  e = hipLaunchKernel(k->fn_a, dim3((unsigned)tiles_a, (unsigned)p.P), dim3(kNTA), args, lds_a, stream);
-  if (e == hipSuccess)
-    e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
-  if (e == hipSuccess) e = hipLaunchKernel(k->fn_c, grid, dim3(NT), args, lds_c, stream);
+  // FP64: phases A, B, C once.  FP32: the same with the interior solve in
+  // FP32, then per refinement iteration the three phases on the residual,
+  // phase C adding its correction to x
+  for (int it = 0; it <= iters && e == hipSuccess; ++it) {
+    const void *fa = it == 0 ? k->fn_a : k->fn_a_res;
+    const void *fc = !fp32 ? k->fn_c : (it == 0 ? k->fn_c32 : k->fn_c32_res);
+    e = hipLaunchKernel(fa, dim3((unsigned)tiles_a, (unsigned)p.P), dim3(kNTA), args, lds_a, stream);
+    if (e == hipSuccess)
+      e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
+    if (e == hipSuccess) e = hipLaunchKernel(fc, grid, dim3(NT), args, lds_c, stream);
+  }
   const hipError_t e2 = fs ? hipSuccess : hipFreeAsync(scratch, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
@@ -524,11 +543,12 @@ cb_status solve_entry(cb_plan_t plan, const cb_grid *grid, int32_t axis, const d
   Geo g;
   if ((s = geometry(grid, axis, g))) return s;
   if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
-  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
-    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
   if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
   if (!b || !x) return fail(CB_ERR_INVALID_ARG, "b and x must be non-NULL");
   if (b != x && overlap(b, x, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "b and x overlap");
+  // partitioned refinement re-reads b after x has been written
+  if (b == x && plan->p.P > 1 && plan->p.refine_iters > 0)
+    return fail(CB_ERR_UNSUPPORTED, "partitioned FP32 + refinement solves need b and x apart (not in place)");
   if (plan->p.P == 1) return launch_line(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream), fs);
   return launch_wg(plan->p, g, b, x, nullptr, static_cast<hipStream_t>(stream), fs);
 }
@@ -630,8 +650,6 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
   if ((s = geometry(grid, axis, g))) return s;
   if (g.n != plan->p.n) return fail(CB_ERR_INVALID_ARG, "grid extent along axis differs from plan n");
   if (!plan->p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "the fused stencil needs a cyclic plan");
-  if (plan->p.P != 1 && plan->p.precision != CB_FP64)
-    return fail(CB_ERR_UNSUPPORTED, "partitioned lines (P > 1) are FP64 only");
   if (g.nlines == 0) return CB_OK;  // empty grid: nothing is read or written
   if (!f || !out) return fail(CB_ERR_INVALID_ARG, "f and out must be non-NULL");
   if (overlap(f, out, span_elems(grid))) return fail(CB_ERR_INVALID_ARG, "f and out overlap");

@@ -69,6 +69,10 @@ struct WgArgs {
   int kw;                    // their window length
   int wave_local;            // phase C: every line lies in one wavefront (its
                              // exchanges need only wavefront-local ordering)
+  int sc_stride;             // scratch doubles per (line, partition): 3R, or 4R
+                             // when refining (+ the current x at the interface rows)
+  int band_rows;             // FP64 residual: 1 reads bands per row, 0 band_c
+  double band_c[2 * kMaxR + 1];  // constant bands a_{-R..R}
 };
 
 struct StencilArgs {
@@ -89,7 +93,10 @@ struct WgKernel {
   int R, M, mode, Q;
   bool ilu;                        // lane interiors by banded elimination
   int max_threads;                 // workgroup size bound of phases A and C
-  const void *fn_a, *fn_b, *fn_c;  // phases A (interiors), B (reduced system), C (back-substitution)
+  const void *fn_a, *fn_b, *fn_c;  // phases A (interface data), B (reduced system), C (interiors)
+  // FP32 + FP64 refinement: phase A forming the residual b - A x, phase C
+  // with an FP32 interior solve storing x, and adding its correction to x
+  const void *fn_a_res, *fn_c32, *fn_c32_res;
 };
 
 // Persistent batched launch: queue header and one work-table entry per item.
@@ -133,6 +140,8 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
 const LineKernel *find_copy_kernel(int M, int mode, bool uni);
 const BatchKernel *find_batch_kernel(int R, int M, int fp32, bool uni, bool ilu, int mode, int Q);
 const WgKernel *find_wg_kernel(int R, int M, int mode, int Q, bool ilu);
+// FP32 + refinement instances of the partitioned kernels (wg_fp32.hip)
+const WgKernel *find_wg32_kernel(int R, int M, int mode, int Q, bool ilu);
 const void *stencil_kernel();
 
 }  // namespace cb

@@ -923,13 +923,12 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     return CB_ERR_INVALID_ARG;
   }
   const int R = d.r, n = d.n, W = 2 * R + 1;
-  // partitions 0: one workgroup per line while a line fits one (16384 rows:
-  // 1024 lanes of 16), else FP64 lines split into ~1024-row workgroup
-  // partitions (measured fastest among 512-, 1024- and 2048-row ones at
-  // n = 8192), at most 64
-  const int P = d.partitions > 0                          ? d.partitions
-                : (d.precision == CB_FP64 && n > 16384) ? std::min(64, (n + 1023) / 1024)
-                                                          : 1;
+  // partitions 0: one workgroup per line while a line fits one (FP64 16384
+  // rows: 1024 lanes of 16; FP32 8192: 512 lanes of 16), else ~1024-row
+  // workgroup partitions (measured fastest among 512-, 1024- and 2048-row
+  // ones at n = 8192), at most 64
+  const int one_wg_rows = d.precision == CB_FP64 ? 16384 : 8192;
+  const int P = d.partitions > 0 ? d.partitions : (n > one_wg_rows ? std::min(64, (n + 1023) / 1024) : 1);
   if (P > 64) {
     msg = "at most 64 workgroup partitions per line";
     return CB_ERR_UNSUPPORTED;

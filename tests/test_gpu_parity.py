@@ -270,6 +270,49 @@ def test_copy_lines_moves_the_data_unchanged(gpu, axis, n, prec):
             cb.copy_lines(plan8, g, axis, out=torch.empty_like(g))
 
 
+@pytest.mark.parametrize("P", [4, 7, 16])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bands", ["tri", "penta", "hept"])
+def test_partitioned_fp32_refinement(gpu, P, axis, bands):
+    """FP32 + FP64 refinement across workgroup partitions: every iteration
+    runs the partitioned solve (interiors in FP32) on the FP64 residual.
+    Solve (cyclic and acyclic) and fused derivative to 1e-12 with the
+    automatic count; plain FP32 to its bound; in place is refused."""
+    bd, sch = dict(tri=(TRI, schemes.DERIV6), penta=(PENTA, schemes.DERIV10), hept=(HEPT, schemes.DERIV12H))[bands]
+    n = 200 * P + 3
+    shape = shape_with(axis, n, (5, 6))
+    b = synth.random_uniform(shape, seed=P + 10 * axis)
+    bdev = b.to(gpu)
+    for cyclic in (True, False):
+        plan = cb.Plan(bd, n, partitions=P, precision="fp32_refine", cyclic=cyclic)
+        assert plan.info()["refine_iters"] >= 1
+        x = cb.solve(plan, bdev, axis).cpu().numpy()
+        assert relerr(x, oracle.solve_axis(b.numpy(), axis, bd, cyclic=cyclic)) <= 1e-12, cyclic
+        with pytest.raises(cb.CbError):  # in place: b is needed again after x is written
+            cb.solve(plan, bdev, axis, out=bdev)
+    f, _ = synth.random_modes(shape, seed=P)
+    lo, c = deriv_stencil(sch, n)
+    ref = oracle.apply_axis(f.numpy(), axis, bd, lo, c)
+    plan = cb.Plan(bd, n, partitions=P, precision="fp32_refine")
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out, ref) <= 1e-12
+    plan32 = cb.Plan(bd, n, partitions=P, precision="fp32")
+    out32 = cb.apply_derivative(plan32, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out32, ref) <= fp32_bound(bd)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_long_fp32_lines_default_partitions(gpu, axis):
+    """FP32 + refinement lines longer than one workgroup (n > 8192) are split
+    into ~1024-row partitions by default."""
+    n = 12000
+    plan = cb.Plan(TRI, n, precision="fp32_refine")
+    assert plan.info()["partitions"] == 12
+    b = synth.random_uniform(shape_with(axis, n, (3, 4)), seed=axis)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    assert relerr(x, oracle.solve_axis(b.numpy(), axis, TRI)) <= 1e-12
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192

@@ -371,16 +371,16 @@ def test_automatic_refinement_count():
 
 
 def test_automatic_partition_count():
-    """partitions 0: one workgroup per line up to 16384 rows, else FP64 lines
-    in ceil(n / 1024) workgroup partitions (at most 64); FP32 lines longer
-    than a workgroup are rejected."""
+    """partitions 0: one workgroup per line up to 16384 rows in FP64 (8192 in
+    FP32), else ceil(n / 1024) workgroup partitions (at most 64)."""
     tri = [1 / 3, 1.0, 1 / 3]
     for n, want in ((512, 1), (16384, 1), (16385, 17), (32768, 32), (50000, 49), (100000, 64)):
         info = cb.Plan(tri, n, host_only=True).info()
         assert info["partitions"] == want, n
     assert cb.Plan(tri, 32768, partitions=4, host_only=True).info()["partitions"] == 4
-    with pytest.raises(cb.CbError):
-        cb.Plan(tri, 32768, precision="fp32_refine", host_only=True)
+    for n, want in ((8192, 1), (8193, 9), (32768, 32)):
+        info = cb.Plan(tri, n, precision="fp32_refine", host_only=True).info()
+        assert info["partitions"] == want and info["refine_iters"] == 1, n
 
 
 @pytest.mark.parametrize("n", [512, 8192])
