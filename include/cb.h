@@ -220,13 +220,18 @@ typedef struct {
  * (a class is r, rows per lane, arithmetic, uniform or general lane layout,
  * interior solve, unit-stride or strided rows and stencil half-width (2 or
  * 3), as an item's plan, row stride and stencil select them; a batch of plans built alike for one scheme and
- * precision is usually a few classes).  Every plan must have partitions = 1 and be cyclic when a
- * stencil is given; n, axis, grid, stencil, precision and refinement count
- * may differ between items.  Each line goes through the same arithmetic as
- * in a single cb_solve / cb_apply_derivative call with the same plan.
+ * precision is usually a few classes).  Items whose plan splits lines over
+ * P > 1 workgroup partitions (Sec. 3-4) run after those as their own phase
+ * launches (three per solve and refinement iteration), with their partition
+ * scratch in the workspace.  A plan must be cyclic when a stencil is given;
+ * n, P, axis, grid, stencil, precision and refinement count may differ
+ * between items.  Each line goes through the same arithmetic as in a single
+ * cb_solve / cb_apply_derivative call with the same plan.
  *
  * `workspace` is a caller-owned DEVICE buffer of at least
- * cb_batch_workspace_size(n_items) bytes holding the queue and work table.
+ * cb_batch_workspace_bytes(items, n_items) bytes holding the queue, the work
+ * table and the partition scratch of P > 1 items; without such items that
+ * is cb_batch_workspace_size(n_items).
  * cb_batch_build validates the items and enqueues the upload of the table on
  * `stream` from a pinned host buffer the library keeps per workspace; it does
  * not wait for the upload (only for the workspace's previous one), so the
@@ -243,6 +248,7 @@ typedef struct {
  * instead (each item's tiles in the order its single launch would take;
  * measured the faster form). */
 size_t cb_batch_workspace_size(int32_t n_items);
+size_t cb_batch_workspace_bytes(const cb_batch_item *items, int32_t n_items);
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace,
                          size_t workspace_bytes, void *stream);
 cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream);

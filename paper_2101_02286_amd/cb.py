@@ -17,7 +17,7 @@ CB_OK, CB_ERR_INVALID_ARG, CB_ERR_UNSUPPORTED, CB_ERR_SINGULAR, CB_ERR_OOM, CB_E
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_refine": 2}
 ABI_SYMBOLS = ("cb_plan", "cb_plan_destroy", "cb_rhs_stencil", "cb_solve", "cb_apply_derivative",
                "cb_solve_noalloc", "cb_copy_lines",
-               "cb_batch_workspace_size", "cb_batch_build", "cb_batch_launch", "cb_solve_batched",
+               "cb_batch_workspace_size", "cb_batch_workspace_bytes", "cb_batch_build", "cb_batch_launch", "cb_solve_batched",
                "cb_plan_get_info",
                "cb_plan_get_schedule", "cb_plan_get_array", "cb_last_error")
 
@@ -82,6 +82,8 @@ def lib():
         L.cb_apply_derivative.argtypes = [vp, ctypes.POINTER(StencilC), ctypes.POINTER(Grid), i32, vp, vp, vp]
         L.cb_batch_workspace_size.argtypes = [i32]
         L.cb_batch_workspace_size.restype = ctypes.c_size_t
+        L.cb_batch_workspace_bytes.argtypes = [ctypes.POINTER(BatchItem), i32]
+        L.cb_batch_workspace_bytes.restype = ctypes.c_size_t
         L.cb_solve_batched.argtypes = [ctypes.POINTER(BatchItem), i32, vp, ctypes.c_size_t, i32, vp]
         L.cb_batch_build.argtypes = [ctypes.POINTER(BatchItem), i32, vp, ctypes.c_size_t, vp]
         L.cb_batch_launch.argtypes = [vp, i32, vp]

@@ -31,10 +31,23 @@ struct BatchLaunch {
   int threads;
   int64_t tiles;
 };
+// An item whose plan splits lines over P > 1 workgroup partitions: it runs
+// as its own phase launches, with its partition scratch in the workspace.
+struct WgItem {
+  cb_plan_t plan;
+  cb_grid grid;
+  int axis;
+  const double *in;
+  double *out;
+  bool has_stencil;
+  cb_stencil stencil;
+  size_t sc_off, sc_bytes;
+};
 // Per workspace: its launches, the pinned host copy its table is uploaded
 // from, and the event recorded on the build stream after that upload.
 struct BatchState {
   std::vector<BatchLaunch> launches;
+  std::vector<WgItem> wg_items;
   hipStream_t stream = nullptr;
   hipEvent_t copied = nullptr;
   char *pinned = nullptr;
@@ -255,6 +268,30 @@ cb_status check_stencil(const cb_stencil *st) {
 
 cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                     hipStream_t stream, const FixedScratch *fs);
+
+// Partition scratch of a P > 1 launch: b~, the two ends of y and, when
+// refining, the current x at the interface rows, per (line, partition).
+size_t wg_scratch_bytes(const Plan &p, int64_t nlines) {
+  const int stride = (p.precision != CB_FP64 && p.refine_iters > 0 ? 4 : 3) * p.R;
+  return (size_t)nlines * p.P * stride * sizeof(double);
+}
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Workspace bytes of a batch: queue headers and work table, then from a
+// 256-byte boundary the partition scratch of each P > 1 item.
+size_t batch_bytes(const cb_batch_item *items, int32_t n_items) {
+  const size_t nn = (size_t)(n_items > 0 ? n_items : 0);
+  const size_t table = batch_items_offset(nn) + nn * sizeof(BatchItemDev);
+  size_t scratch = 0;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const cb_batch_item &it = items[i];
+    if (!it.plan || it.plan->p.P == 1) continue;
+    Geo g;
+    if (geometry(&it.grid, it.axis, g) != CB_OK) continue;
+    scratch += align256(wg_scratch_bytes(it.plan->p, g.nlines));
+  }
+  return scratch ? align256(table) + scratch : table;
+}
 
 // Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
 // turn, so in launch order neighbouring tiles run on different XCDs):
@@ -484,7 +521,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // in consecutive lanes), strided lines 64 adjacent ones per row access
   constexpr int kNTA = 256;
   const int WA = mode == MODE_X ? kNTA / 64 : 64;
-  const size_t sbytes = (size_t)g.nlines * p.P * a.sc_stride * sizeof(double);
+  const size_t sbytes = wg_scratch_bytes(p, g.nlines);
   void *scratch = nullptr;
   hipError_t e = hipSuccess;
   if (fs) {
@@ -681,8 +718,12 @@ size_t cb_batch_workspace_size(int32_t n_items) {
 cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,
                          void *stream) {
   if (!items || n_items <= 0) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: no items");
-  if (!workspace || workspace_bytes < cb_batch_workspace_size(n_items))
-    return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace missing or too small");
+  const size_t need = batch_bytes(items, n_items);
+  if (!workspace || workspace_bytes < need)
+    return fail(CB_ERR_INVALID_ARG, "cb_batch_build: workspace missing or too small (needs " + std::to_string(need) +
+                                        " bytes: cb_batch_workspace_bytes)");
+  std::vector<WgItem> wg_items;
+  size_t sc_next = align256(batch_items_offset((size_t)n_items) + (size_t)n_items * sizeof(BatchItemDev));
   struct Cls {
     int R, M, fp;
     bool uni, ilu;
@@ -700,7 +741,6 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     cb_status s = check_plan_for_solve(it.plan);
     if (s) return s;
     const Plan &p = it.plan->p;
-    if (p.P != 1) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: plans must have partitions = 1");
     Geo g;
     if ((s = geometry(&it.grid, it.axis, g))) return s;
     if (g.n != p.n) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: grid extent differs from plan n");
@@ -712,6 +752,22 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       if (!p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: a stencil needs a cyclic plan");
     }
     if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: more than 2^31 lines");
+    if (p.P != 1) {  // its own phase launches, scratch in the workspace
+      WgItem w;
+      w.plan = it.plan;
+      w.grid = it.grid;
+      w.axis = it.axis;
+      w.in = it.in;
+      w.out = it.out;
+      w.has_stencil = it.stencil != nullptr;
+      if (it.stencil) w.stencil = *it.stencil;
+      w.sc_bytes = wg_scratch_bytes(p, g.nlines);
+      w.sc_off = sc_next;
+      sc_next += align256(w.sc_bytes);
+      wg_items.push_back(w);
+      cls_of[i] = -1;
+      continue;
+    }
     // the plan's lane layout for this item's row stride, as a single launch uses
     const int si = g.rs == 1 ? 0 : p.seg_s;
     const SegPlan &sp = p.segs[si];
@@ -819,7 +875,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       if (overlap2(items[i].out, span_elems(&items[i].grid), items[j].out, span_elems(&items[j].grid)))
         return fail(CB_ERR_INVALID_ARG, "cb_batch_build: outputs of two items overlap");
   // workspace: one queue header per class, then the work table grouped by class
-  std::vector<char> host(cb_batch_workspace_size(n_items), 0);
+  std::vector<char> host(batch_items_offset((size_t)n_items) + (size_t)n_items * sizeof(BatchItemDev), 0);
   std::vector<BatchLaunch> launches;
   size_t slot = 0;
   for (size_t c = 0; c < cls.size(); ++c) {
@@ -878,24 +934,28 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
   if (e == hipSuccess) e = hipEventRecord(bs.copied, st);
   if (e != hipSuccess) {
     bs.launches.clear();
+    bs.wg_items.clear();
     return hip_fail(e, "cb_batch_build: copy");
   }
   bs.stream = st;
   bs.launches = std::move(launches);
+  bs.wg_items = std::move(wg_items);
   return CB_OK;
 }
 
 cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
   if (!workspace) return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace is NULL");
   std::vector<BatchLaunch> ls;
+  std::vector<WgItem> wgs;
   hipStream_t built_on = nullptr;
   hipEvent_t copied = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     auto itr = g_batch.find(workspace);
-    if (itr == g_batch.end() || itr->second.launches.empty())
+    if (itr == g_batch.end() || (itr->second.launches.empty() && itr->second.wg_items.empty()))
       return fail(CB_ERR_INVALID_ARG, "cb_batch_launch: workspace was not built");
     ls = itr->second.launches;
+    wgs = itr->second.wg_items;
     built_on = itr->second.stream;
     copied = itr->second.copied;
   }
@@ -944,7 +1004,24 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
     e = hipLaunchKernel(l.fn, dim3(ctas), dim3(l.threads), args, l.lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "cb_batch_launch: kernel launch");
   }
+  // items split over workgroup partitions: their phase launches, with the
+  // partition scratch in the workspace (no allocation, so capturable)
+  for (const WgItem &w : wgs) {
+    Geo g;
+    cb_status s = geometry(&w.grid, w.axis, g);
+    if (s) return s;
+    if (g.nlines == 0) continue;
+    const FixedScratch fs{static_cast<char *>(workspace) + w.sc_off, w.sc_bytes};
+    s = launch_wg(w.plan->p, g, w.in, w.out, w.has_stencil ? &w.stencil : nullptr, static_cast<hipStream_t>(stream),
+                  &fs);
+    if (s) return s;
+  }
   return CB_OK;
+}
+
+size_t cb_batch_workspace_bytes(const cb_batch_item *items, int32_t n_items) {
+  if (!items || n_items <= 0) return cb_batch_workspace_size(n_items);
+  return batch_bytes(items, n_items);
 }
 
 cb_status cb_solve_batched(const cb_batch_item *items, int32_t n_items, void *workspace, size_t workspace_bytes,

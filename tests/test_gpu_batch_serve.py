@@ -39,7 +39,7 @@ def batch(items, stream=None):
         arr[i].inp = f.data_ptr()
         arr[i].out = out.data_ptr()
         keep.append(st)
-    need = cb.lib().cb_batch_workspace_size(len(items))
+    need = cb.lib().cb_batch_workspace_bytes(arr, len(items))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     s = stream or torch.cuda.current_stream()
     cb._check(cb.lib().cb_batch_build(arr, len(items), cb.ctypes.c_void_p(ws.data_ptr()), need,
@@ -145,6 +145,83 @@ def test_mixed_plans_one_batch(gpu):
             got = out.cpu().numpy()
             assert relerr(got, ref) <= 1e-12
             assert np.array_equal(got, single.cpu().numpy())
+
+
+def _partitioned_batch_items(gpu):
+    """Items split over workgroup partitions (FP64 and FP32 + refinement,
+    fused and plain, cyclic and acyclic, r = 1..3) beside one-partition ones."""
+    HEPT = schemes.bands_collocated(schemes.DERIV12H)
+    cases = [  # (bands, scheme, n, P, precision, axis, fused, cyclic)
+        (TRI, "tri6", 4096, 4, "fp64", 0, True, True), (PENTA, "penta10", 3003, 3, "fp32_refine", 2, True, True),
+        (TRI, "tri6", 2000, 5, "fp64", 1, False, False), (HEPT, "hept12", 2048, 4, "fp32_refine", 0, False, True),
+        (TRI, "tri6", 256, 1, "fp64", 1, True, True), (PENTA, "penta10", 300, 1, "fp32_refine", 0, False, True),
+    ]
+    items, singles, refs = [], [], []
+    for k, (bands, scheme, n, P, prec, axis, fused, cyclic) in enumerate(cases):
+        shape = [6, 5]
+        shape.insert(axis, n)
+        shape = (shape[2], shape[1], shape[0])
+        plan = cb.Plan(bands, n, partitions=P, precision=prec, cyclic=cyclic)
+        assert plan.info()["partitions"] == P
+        if fused:
+            f, _ = synth.random_modes(shape, seed=k)
+            lo, c = stencil_for(scheme, n)
+            st = cb.Stencil(lo, c)
+            refs.append(oracle.apply_axis(f.numpy(), axis, bands, lo, c))
+            fd = f.to(gpu)
+            singles.append(cb.apply_derivative(plan, st, fd, axis))
+        else:
+            b = synth.random_uniform(shape, seed=k)
+            st = None
+            refs.append(oracle.solve_axis(b.numpy(), axis, bands, cyclic=cyclic))
+            fd = b.to(gpu)
+            singles.append(cb.solve(plan, fd, axis))
+        items.append((plan, st, fd, torch.empty_like(fd), axis))
+    return items, singles, refs
+
+
+def test_batch_with_partitioned_items(gpu):
+    """P > 1 items run as their own phase launches after the line classes,
+    with their scratch in the workspace: each matches the oracle and is
+    bitwise equal to its single call."""
+    items, singles, refs = _partitioned_batch_items(gpu)
+    ws = batch(items)
+    assert ws.numel() > cb.lib().cb_batch_workspace_size(len(items))
+    for max_ctas in (5, -1):
+        for it in items:
+            it[3].fill_(float("nan"))
+        launch(ws, max_ctas=max_ctas)
+        torch.cuda.synchronize()
+        for (plan, st, fd, out, axis), single, ref in zip(items, singles, refs):
+            got = out.cpu().numpy()
+            assert relerr(got, ref) <= 1e-12
+            assert np.array_equal(got, single.cpu().numpy())
+
+
+def test_graph_replay_with_partitioned_items(gpu):
+    """The batched launch with P > 1 items captured once in a HIP graph and
+    replayed several times, with eager work between the replays: every
+    replay equals the eager result."""
+    items, singles, refs = _partitioned_batch_items(gpu)
+    ws = batch(items)
+    torch.cuda.synchronize()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=gs):
+        launch(ws, stream=gs, max_ctas=-1)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for it in items:
+            it[3].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device=gpu).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        for (plan, st, fd, out, axis), single in zip(items, singles):
+            assert torch.equal(out, single), rep
+    del junk
 
 
 def test_batch_with_empty_items(gpu):
