@@ -279,6 +279,11 @@ typedef struct {
   int32_t boundary_window;       /* P > 1: rows at each end of an interior
                                     block that phase A reads (the kept part
                                     of the boundary rows of D_i^{-1}) */
+  int32_t fullblock_seg;         /* P > 1: segment index (cb_plan_get_array)
+                                    of the full-block lane plan phase C uses
+                                    on unit-stride launches, -1 when phase C
+                                    solves each interior block D_i itself */
+  int32_t fullblock_seg_strided; /* the same for strided launches */
 } cb_plan_info;
 cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info);
 

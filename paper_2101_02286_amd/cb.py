@@ -61,7 +61,9 @@ class PlanInfo(ctypes.Structure):
                                          ("interior_elimination", ctypes.c_int32),
                                          ("interior_elimination_strided", ctypes.c_int32),
                                          ("partitions_strided", ctypes.c_int32),
-                                         ("boundary_window", ctypes.c_int32)]
+                                         ("boundary_window", ctypes.c_int32),
+                                         ("fullblock_seg", ctypes.c_int32),
+                                         ("fullblock_seg_strided", ctypes.c_int32)]
 
 
 def lib():

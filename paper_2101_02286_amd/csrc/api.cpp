@@ -447,7 +447,11 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
                            : find_wg_kernel(p.R, M, mode, Q, p.segs[so].ilu != 0);
   if (!k) return fail(CB_ERR_UNSUPPORTED, "no partitioned kernel for this layout");
   const int iters = fp32 ? p.refine_iters : 0;  // refinement iterations after the first solve
-  const int L = p.segs[so].L;
+  // FP64 phase C on whole partitions when the plan has a full-block plan for
+  // this layout (equal partitions of L*M rows, constant bands)
+  const int fbi = mode == MODE_S ? p.fb_seg_s : p.fb_seg_u;
+  const bool use_fb = fbi >= 0 && !fp32 && k->fn_c_fb != nullptr && p.desc.x_staging != 1;
+  const int L = use_fb ? p.segs[fbi].L : p.segs[so].L;
   int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
   NT = std::min(std::max(NT, L), k->max_threads);
@@ -457,12 +461,14 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int RSw = 2 * std::max(p.R, Q);
   size_t coef_doubles = 0;
   for (int i = so; i < so + p.P; ++i) coef_doubles = std::max(coef_doubles, (size_t)p.segs[i].ntypes * p.segs[i].block);
-  const bool coef_lds = coef_doubles * 8 <= 16384;
+  // (the full-block form reads one coefficient block through the scalar cache)
+  const bool coef_lds = coef_doubles * 8 <= 16384 && !use_fb;
   const size_t extra = coef_lds ? coef_doubles : 0;
   // unit-stride lines are loaded and stored through an LDS tile of W lines
   const bool stage_x = mode == MODE_X && p.desc.x_staging != 1;
   int smax = 0;
   for (int i = so; i < so + p.P; ++i) smax = std::max(smax, p.segs[i].S);
+  if (use_fb) smax = p.segs[fbi].S;
   const int64_t pitch = stage_x ? smax + smax / M + 1 : 0;
   auto lds_c_of = [&](int nt) { return ((size_t)nt * 2 * RSw + extra + (size_t)(nt / L) * pitch) * 8; };
   // phase B: one thread per (line, partition), 256-thread blocks
@@ -517,6 +523,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
     a.band_rows = (p.desc.per_row || !p.desc.cyclic) ? 1 : 0;
   }
   a.wave_local = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 1 : 0;
+  a.fb = use_fb ? p.segdev + fbi : nullptr;
+  a.fb_type = use_fb ? (mode == MODE_S ? p.fb_type_s : p.fb_type_u) : 0;
   // phase A: 256 threads; a unit-stride line per wavefront (consecutive rows
   // in consecutive lanes), strided lines 64 adjacent ones per row access
   constexpr int kNTA = 256;
@@ -549,7 +557,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // phase C adding its correction to x
   for (int it = 0; it <= iters && e == hipSuccess; ++it) {
     const void *fa = it == 0 ? k->fn_a : k->fn_a_res;
-    const void *fc = !fp32 ? k->fn_c : (it == 0 ? k->fn_c32 : k->fn_c32_res);
+    const void *fc = !fp32 ? (use_fb ? k->fn_c_fb : k->fn_c) : (it == 0 ? k->fn_c32 : k->fn_c32_res);
     e = hipLaunchKernel(fa, dim3((unsigned)tiles_a, (unsigned)p.P), dim3(kNTA), args, lds_a, stream);
     if (e == hipSuccess)
       e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
@@ -1056,6 +1064,8 @@ cb_status cb_plan_get_info(cb_plan_t plan, cb_plan_info *info) {
   info->interior_elimination_strided = p.segs.empty() ? 0 : p.segs[p.seg_s].ilu;
   info->partitions_strided = p.strided_wg ? p.strided_wg->P : p.P;
   info->boundary_window = p.Kw;
+  info->fullblock_seg = p.fb_seg_u;
+  info->fullblock_seg_strided = p.fb_seg_s;
   return CB_OK;
 }
 

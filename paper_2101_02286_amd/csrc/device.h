@@ -136,14 +136,19 @@ __device__ __forceinline__ void stage_coef(const SegDev &sg, T *dst, int tid, in
 // Solve the segment in place: on entry v[0..m) holds b of the lane's rows, on
 // exit x.  Padding slots (k >= m) hold zero and stay zero.  `cl` is the LDS
 // copy of the coefficient blocks when CSRC == CSRC_LDS.
-template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL, bool ILU = false>
+// UACYC (with UNI: every lane holds M rows): an acyclic segment whose lanes
+// all read the coefficient block `type`, except that lane 0's interface rows
+// are identity equations (x~ = b, its couplings to other lanes zero) and the
+// last lane has no forward coupling; the reduced-system multipliers are read
+// per lane.  Used for whole workgroup partitions (the full-block plans).
+template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL, bool ILU = false, bool UACYC = false>
 __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const LanePos &p, int type,
                                               int m, Xchg &xc, const T *cl = nullptr) {
   constexpr int N = M - R;
   constexpr int TI = ceil_log2_c(N);
   constexpr int RR = R * R;
   constexpr CoefOff off = coef_offsets(R, M, TI, ILU);
-  const T *cf = (CSRC == CSRC_LDS ? cl : coef_of<T>(sg)) + (size_t)(UNI ? 0 : type) * sg.block;
+  const T *cf = (CSRC == CSRC_LDS ? cl : coef_of<T>(sg)) + (size_t)((UNI && !UACYC) ? 0 : type) * sg.block;
 
   T y[N];
 #pragma unroll
@@ -203,12 +208,12 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     T acc = v[a];
 #pragma unroll
     for (int c = 0; c < R; ++c) acc -= cget<CSRC>(cf + off.Lt + a * R + c) * yprev[c] + cget<CSRC>(cf + off.Ut + a * R + c) * y[c];
-    xt[a] = acc;
+    xt[a] = (UACYC && p.l == 0) ? v[a] : acc;  // identity rows: x~ = b
   }
 
   // ---- reduced cyclic block system across lanes: block PCR (Alg. 3) ----
   const T *rd = red_of<T>(sg);
-  const int lr = UNI ? 0 : p.l;
+  const int lr = (UNI && !UACYC) ? 0 : p.l;
   for (int t = 0; t < sg.Tred; ++t) {
     const int s = 1 << t;
     xc.publish(p.tid, xt);
@@ -248,6 +253,10 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
   T xnext[R];
   xc.fetch(p.tid_of((p.l + 1) & (p.L - 1)), xnext);
   xc.done();
+  if (UACYC && p.l == p.L - 1) {  // the acyclic segment ends: no forward coupling
+#pragma unroll
+    for (int c = 0; c < R; ++c) xnext[c] = (T)0;
+  }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     T acc = y[j];

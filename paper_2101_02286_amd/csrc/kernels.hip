@@ -71,7 +71,8 @@ const LineKernel *find_line_kernel(int R, int M, int fp32, int mode, int Q, bool
 
 #define CB_WG_INST(R, M, MODE, Q, ILU)                                                                 \
   {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, MODE, Q>,                      \
-   (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q, ILU>, nullptr, nullptr, nullptr}
+   (const void *)&k_wg_b<R>, (const void *)&k_wg_c<R, M, MODE, Q, ILU>, nullptr, nullptr, nullptr,        \
+   ILU ? (const void *)&k_wg_c<R, M, MODE, Q, true, double, false, true> : nullptr}
 #define CB_WG_I(R, M, MODE, Q) CB_WG_INST(R, M, MODE, Q, false), CB_WG_INST(R, M, MODE, Q, true)
 #define CB_WG_Q(R, M, MODE) CB_WG_I(R, M, MODE, 0), CB_WG_I(R, M, MODE, 2), CB_WG_I(R, M, MODE, 3)
 static const WgKernel kWgKernels[] = {

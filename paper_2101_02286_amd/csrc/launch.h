@@ -71,6 +71,8 @@ struct WgArgs {
                              // exchanges need only wavefront-local ordering)
   int sc_stride;             // scratch doubles per (line, partition): 3R, or 4R
                              // when refining (+ the current x at the interface rows)
+  const SegDev *fb;          // phase C on whole partitions: the full-block plan
+  int fb_type;               // ... and its middle lanes' coefficient block
   int band_rows;             // FP64 residual: 1 reads bands per row, 0 band_c
   double band_c[2 * kMaxR + 1];  // constant bands a_{-R..R}
 };
@@ -97,6 +99,7 @@ struct WgKernel {
   // FP32 + FP64 refinement: phase A forming the residual b - A x, phase C
   // with an FP32 interior solve storing x, and adding its correction to x
   const void *fn_a_res, *fn_c32, *fn_c32_res;
+  const void *fn_c_fb;             // FP64 phase C on whole partitions (full-block plans)
 };
 
 // Persistent batched launch: queue header and one work-table entry per item.

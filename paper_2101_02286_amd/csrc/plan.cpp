@@ -1088,6 +1088,47 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     }
     std::swap(m2, msg);  // a strided set that cannot be built leaves the unit-stride one for both
   }
+  // full-block segments for phase C (see plan.h), one per lane-layout set
+  if (!per_row && n % P == 0) {
+    const int sblk = n / P, W2 = 2 * R + 1;
+    std::vector<double> bc(W2);
+    for (int o = 0; o < W2; ++o) bc[o] = p.bands[(size_t)(n / 2) * W2 + o];
+    auto full_block = [&](const SegPlan &like, int &type) -> int {
+      const int M = like.M, L = sblk / M;
+      if (L * M != sblk || !is_pow2(L) || L < 4 || L > 1024 || !like.ilu) return -1;
+      auto coef = [&](int g, int o) -> double {
+        if (g < R) return o == 0 ? 1.0 : 0.0;  // interface rows: x = x~_i
+        const int c = g + o;
+        return (c >= 0 && c < sblk) ? bc[o + R] : 0.0;  // couplings beyond the block move to the RHS
+      };
+      SegPlan fb;
+      std::string m2;
+      if (build_segment(sblk, R, false, true, coef, M, fb, m2, L, PREF_S, 16, 2) != CB_OK || !fb.ilu) return -1;
+      // lane types: first, middle (all alike), last; the first and last may
+      // differ from the middle only in the terms the kernel masks
+      const int t0 = fb.lane_type[0], t1 = fb.lane_type[1], t2 = fb.lane_type[L - 1];
+      for (int l = 1; l < L - 1; ++l)
+        if (fb.lane_type[l] != t1) return -1;
+      const CoefOff off = coef_offsets(R, M, fb.Tint, true);
+      const double *b0 = &fb.coef[(size_t)t0 * fb.block], *b1 = &fb.coef[(size_t)t1 * fb.block],
+                   *b2 = &fb.coef[(size_t)t2 * fb.block];
+      for (int q = 0; q < fb.block; ++q) {
+        const bool ltut = q >= off.Lt && q < off.S, rm = q >= off.Rm;
+        if (b0[q] != (ltut ? 0.0 : b1[q])) return -1;
+        if (b2[q] != (rm ? 0.0 : b1[q])) return -1;
+      }
+      type = t1;
+      p.segs.push_back(std::move(fb));
+      return (int)p.segs.size() - 1;
+    };
+    p.fb_seg_u = full_block(p.segs[0], p.fb_type_u);
+    if (p.seg_s != 0) {
+      p.fb_seg_s = full_block(p.segs[p.seg_s], p.fb_type_s);
+    } else {
+      p.fb_seg_s = p.fb_seg_u;
+      p.fb_type_s = p.fb_type_u;
+    }
+  }
   p.SRg.clear();
   p.SRg_off.assign(P, 0);
   for (int i = 0; i < P; ++i) {

@@ -108,6 +108,15 @@ struct Plan {
   std::vector<double> SRg;             // per partition: S^G [N_i][R] then R^G [N_i][R]
   std::vector<int64_t> SRg_off;        // P
   std::vector<double> LtUtg;           // [P][2][R][R]
+  // Full-block segments (P > 1, equal partitions of L*M rows, constant
+  // bands): the whole partition as one acyclic segment whose first R rows
+  // are identity equations (x = x~_i, known after phase B) and whose
+  // couplings to the next partition move to the right-hand side.  Every lane
+  // then holds M rows, and the lanes' coefficient blocks are one block
+  // (fb_type) apart from lane 0's interface couplings and the last lane's
+  // forward coupling, which are zero: phase C runs the uniform lane code
+  // with those two terms masked.  Indices into segs, -1 when absent.
+  int fb_seg_u = -1, fb_seg_s = -1, fb_type_u = 0, fb_type_s = 0;
   // rows 0..R-1 and N_i-R..N_i-1 of D_i^{-1} over windows of Kw rows at the
   // ends of D_i (entries beyond the window are below 2^-56 of the row's
   // absolute sum): [P][2][R][Kw], first-end window rows 0..Kw-1, last-end

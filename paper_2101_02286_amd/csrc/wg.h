@@ -77,7 +77,11 @@ __device__ __forceinline__ int tile_at(int e) {
 // residual b - A x of the current x, whose rows this lane holds in xo on
 // return (xif0 / xif1: x at this partition's and the next one's interface
 // rows, from the scratch array).
-template <int R, int M, int MODE, int Q, bool ADJ, bool ILU, typename T = double, bool RES = false>
+// FB: the whole partition as one block (the full-block plan a.fb): its
+// first R rows take the interface values x~_i as identity equations, every
+// lane holds M rows and reads the middle lanes' coefficient block through
+// the scalar cache (solve_segment's UACYC form).
+template <int R, int M, int MODE, int Q, bool ADJ, bool ILU, typename T = double, bool RES = false, bool FB = false>
 __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos &p, bool active,
                                                   int64_t base, int part, Xchg &xc, double (&v)[M],
                                                   int &start, int &m, double *coef_lds, double *tb,
@@ -87,11 +91,19 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   // couplings of the block's end rows to the interface values, the
   // coefficient blocks) is issued together with the data, so the workgroup
   // waits for one round trip to memory instead of several in a row.
-  const SegDev &sg = a.segs[part];
-  lane_rows(sg.S, p.lgL, p.l, start, m);
-  const int type = sg.lane_type[p.l];
+  const SegDev &sg = FB ? *a.fb : a.segs[part];
+  int type;
+  if (FB) {
+    start = p.l * M;
+    m = M;
+    type = a.fb_type;
+  } else {
+    lane_rows(sg.S, p.lgL, p.l, start, m);
+    type = sg.lane_type[p.l];
+  }
   const int S = sg.S;
-  const int64_t seg0 = a.wg_start[part] + R;  // first row of the interior block D_i
+  // first row of the block: D_i, or with FB the partition's first row
+  const int64_t seg0 = a.wg_start[part] + (FB ? 0 : R);
   const int64_t row0 = seg0 + start;
   const bool staged = MODE == MODE_X && tb != nullptr;
   constexpr int QQ = Q > 0 ? Q : 1;
@@ -142,7 +154,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   for (int c = 0; c < R; ++c) head[c] = tail[c] = 0.0;
   if (ADJ) {
     constexpr int W2 = 2 * R + 1;
-    if (p.l == 0) {
+    if (p.l == 0 && !FB) {
 #pragma unroll
       for (int c = 0; c < R; ++c) {  // row c of D_i
         const double *bd = a.bands + (seg0 + c) * W2;
@@ -161,7 +173,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
       }
     }
   }
-  if (a.coef_lds) stage_coef<T>(sg, reinterpret_cast<T *>(coef_lds), p.tid, blockDim.x);
+  if (a.coef_lds && !FB) stage_coef<T>(sg, reinterpret_cast<T *>(coef_lds), p.tid, blockDim.x);
   if (staged) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -228,7 +240,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   if (ADJ) {
     if (p.l == 0) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) v[c] -= head[c];
+      for (int c = 0; c < R; ++c) v[c] = FB ? xi[c] : v[c] - head[c];  // FB: the interface rows' values
     }
     if (p.l == p.L - 1) {
 #pragma unroll
@@ -236,7 +248,9 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
         if (k >= m - R && k < m) v[k] -= select_idx(tail, k - (m - R));
     }
   }
-  if constexpr (sizeof(T) == sizeof(double)) {
+  if constexpr (FB) {
+    solve_segment<R, M, T, true, CSRC_GLOBAL, ILU, true>(v, sg, p, type, M, xc);
+  } else if constexpr (sizeof(T) == sizeof(double)) {
     if (a.coef_lds)
       solve_segment<R, M, double, false, CSRC_LDS, ILU>(v, sg, p, type, m, xc, coef_lds);
     else
@@ -478,7 +492,7 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
 // RES: refinement iteration, the interior solve gives a correction that is
 // added to the stored x (the partition's own rows only; the rows it needs
 // from the next partition come from the scratch array).
-template <int R, int M, int MODE, int Q, bool ILU, typename T = double, bool RES = false>
+template <int R, int M, int MODE, int Q, bool ILU, typename T = double, bool RES = false, bool FB = false>
 __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgArgs a) {
   extern __shared__ double smem[];
   constexpr int RS = Q > R ? 2 * Q : 2 * R;
@@ -504,13 +518,13 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
   double v[M], xo[M];
   int start, m;
   double *tb = a.stage_x ? smem + a.stage_off_c + (size_t)p.li * a.stage_pitch : nullptr;
-  wg_solve_interior<R, M, MODE, Q, true, ILU, T, RES>(a, p, active, base, part, xc, v, start, m, smem + a.coef_off_c,
-                                                     tb, xi, xi1, xo, xif0, xif1);
+  wg_solve_interior<R, M, MODE, Q, true, ILU, T, RES, FB>(a, p, active, base, part, xc, v, start, m,
+                                                         smem + a.coef_off_c, tb, xi, xi1, xo, xif0, xif1);
   if (RES) {
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] += xo[k];
   }
-  const int64_t seg0 = a.wg_start[part] + R;
+  const int64_t seg0 = a.wg_start[part] + (FB ? 0 : R);
   if (MODE == MODE_X && tb != nullptr) {
     // mirror of the staged load: every lane has finished reading the tile
     // (its stencil halo) before any lane overwrites it
@@ -519,7 +533,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
     for (int k = 0; k < M; ++k)
       if (k < m) tb[tile_at<M>(start + k)] = v[k];
     xc.sync();
-    const int S = a.segs[part].S;
+    const int S = FB ? a.fb->S : a.segs[part].S;
     double *lout = a.out + base + seg0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -532,7 +546,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
     for (int k = 0; k < M; ++k)
       if (k < m) out[k * a.rs] = v[k];
   }
-  if (!active) return;
+  if (!active || FB) return;  // FB: the interface rows were stored with the block
   if (p.l == 0) {
     const int64_t g0 = a.wg_start[part];
 #pragma unroll

@@ -9,7 +9,8 @@ namespace cb {
 #define CB_WG32_INST(R, M, MODE, Q, ILU)                                                               \
   {R, M, MODE, Q, ILU, wg_max_threads<M, MODE>(), (const void *)&k_wg_a<R, MODE, Q, false>,            \
    (const void *)&k_wg_b<R>, nullptr, (const void *)&k_wg_a<R, MODE, Q, true>,                        \
-   (const void *)&k_wg_c<R, M, MODE, Q, ILU, float, false>, (const void *)&k_wg_c<R, M, MODE, Q, ILU, float, true>}
+   (const void *)&k_wg_c<R, M, MODE, Q, ILU, float, false>, (const void *)&k_wg_c<R, M, MODE, Q, ILU, float, true>, \
+   nullptr}
 #define CB_WG32_I(R, M, MODE, Q) CB_WG32_INST(R, M, MODE, Q, false), CB_WG32_INST(R, M, MODE, Q, true)
 #define CB_WG32_Q(R, M, MODE) CB_WG32_I(R, M, MODE, 0), CB_WG32_I(R, M, MODE, 2), CB_WG32_I(R, M, MODE, 3)
 #define CB_WG32_R(R) CB_WG32_Q(R, 16, MODE_X), CB_WG32_Q(R, 16, MODE_S)

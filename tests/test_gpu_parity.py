@@ -313,6 +313,37 @@ def test_long_fp32_lines_default_partitions(gpu, axis):
     assert relerr(x, oracle.solve_axis(b.numpy(), axis, TRI)) <= 1e-12
 
 
+@pytest.mark.parametrize("P", [4, 16])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bands", ["tri", "penta", "hept"])
+def test_full_block_phase_c(gpu, P, axis, bands):
+    """Equal partitions of L*M rows with constant bands: phase C solves each
+    whole partition as one block (interface rows as identity equations, the
+    uniform lane code with two couplings masked).  Solve (cyclic and acyclic)
+    and fused derivative against the oracle, and against the per-interior
+    form (x_staging = 1 keeps it on unit-stride lines)."""
+    bd, sch = dict(tri=(TRI, schemes.DERIV6), penta=(PENTA, schemes.DERIV10), hept=(HEPT, schemes.DERIV12H))[bands]
+    n = 512 * P
+    shape = shape_with(axis, n, (4, 5))
+    b = synth.random_uniform(shape, seed=P + axis)
+    for cyclic in (True, False):
+        plan = cb.Plan(bd, n, partitions=P, cyclic=cyclic)
+        info = plan.info()
+        assert info["fullblock_seg"] >= 0 and info["fullblock_seg_strided"] >= 0
+        x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        ref = oracle.solve_axis(b.numpy(), axis, bd, cyclic=cyclic)
+        assert relerr(x, ref) <= 1e-12, cyclic
+        if axis == 0:
+            general = cb.Plan(bd, n, partitions=P, cyclic=cyclic, x_staging=1)
+            xg = cb.solve(general, b.to(gpu), axis).cpu().numpy()
+            assert relerr(xg, ref) <= 1e-12 and relerr(x, xg) <= 1e-12
+    f, _ = synth.random_modes(shape, seed=P)
+    lo, c = deriv_stencil(sch, n)
+    plan = cb.Plan(bd, n, partitions=P)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192

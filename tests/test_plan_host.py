@@ -109,6 +109,47 @@ def test_boundary_rows_of_interior_inverse(P, n, name, cyclic):
         assert np.abs(yl[i] - y[:, N - r:]).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("name", ["tri", "penta", "hept"])
+@pytest.mark.parametrize("P,n", [(16, 8192), (8, 8192), (4, 1024)])
+@pytest.mark.parametrize("seg_key", ["fullblock_seg", "fullblock_seg_strided"])
+def test_full_block_segment(name, P, n, seg_key):
+    """Phase C's full-block lane plan: a whole partition whose first r rows
+    are identity equations (the interface values x~_i) and whose couplings to
+    the next partition are moved to the right-hand side.  Solved by the
+    emulated lane scheme with the middle lanes' coefficient block for every
+    lane, lane 0's interface couplings and the last lane's forward coupling
+    masked, it matches a dense solve of that block system."""
+    bands = np.asarray(HEPT if name == "hept" else _bands(name))
+    r = (len(bands) - 1) // 2
+    p = cb.Plan(bands, n, partitions=P, host_only=True)
+    seg = p.info()[seg_key]
+    assert seg >= 0
+    s = n // P
+    rng = np.random.default_rng(s + r)
+    b = rng.standard_normal((2, s))
+    xi, xi1 = rng.standard_normal((2, r)), rng.standard_normal((2, r))
+    v = b.copy()
+    v[:, :r] = xi
+    for c in range(r):  # row s-r+c couples to row s+c+o-r of the next partition
+        for o in range(1, r + 1):
+            if c + o >= r:
+                v[:, s - r + c] -= bands[o + r] * xi1[:, c + o - r]
+    D = np.zeros((s, s))
+    for j in range(s):
+        if j < r:
+            D[j, j] = 1.0
+            continue
+        for o in range(-r, r + 1):
+            if 0 <= j + o < s:
+                D[j, j + o] = bands[o + r]
+    ref = np.linalg.solve(D, v.T).T
+    got = plan_emulator.solve_segment(p, v, seg)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the masked form: every lane takes the middle block
+    types = p.array(3, seg).astype(int)
+    assert len(set(types[1:-1])) == 1
+
+
 def test_boundary_window_is_short_for_compact_schemes():
     """The kept windows of the compact schemes' boundary rows (entries omitted
     below 2^-56 of the row's absolute sum): about 41 rows for alpha = 1/3, 68
