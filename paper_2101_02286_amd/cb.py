@@ -258,3 +258,45 @@ def rhs_stencil(stencil, f, axis, out=None, stream=None):
     _check(lib().cb_rhs_stencil(ctypes.byref(stencil.c), ctypes.byref(g), axis, _dev(f), _dev(out),
                                 _stream(stream)))
     return out
+
+
+def batch_items(items):
+    """ctypes cb_batch_item array of (plan, stencil or None, f, out, axis) tuples."""
+    arr = (BatchItem * len(items))()
+    for i, (plan, st, f, out, axis) in enumerate(items):
+        g = grid_of(f)
+        if grid_of(out).stride[:] != g.stride[:]:
+            raise ValueError("f and out must have the same layout")
+        arr[i].plan = plan.h
+        arr[i].stencil = ctypes.pointer(st.c) if st is not None else None
+        arr[i].grid = g
+        arr[i].axis = axis
+        arr[i].inp = _dev(f).value
+        arr[i].out = _dev(out).value
+    return arr
+
+
+class Batch:
+    """A built batched launch (cb_batch_build) over (plan, stencil or None, f,
+    out, axis) items, with its device workspace sized by
+    cb_batch_workspace_bytes.  launch() runs every item (cb_batch_launch);
+    the plans, stencils and tensors must outlive the batch."""
+
+    def __init__(self, items, stream=None, workspace=None):
+        """`workspace`: a uint8 device tensor to build in when it is large
+        enough (a rebuilt batch may reuse its predecessor's once that one's
+        launches have finished), else a new one is allocated."""
+        self.items = list(items)  # keeps plans, stencils and tensors alive
+        arr = batch_items(self.items)
+        need = lib().cb_batch_workspace_bytes(arr, len(self.items))
+        if workspace is not None and workspace.numel() >= need:
+            self.ws = workspace
+        else:
+            self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.items[0][2].device)
+        _check(lib().cb_batch_build(arr, len(self.items), ctypes.c_void_p(self.ws.data_ptr()), need,
+                                    _stream(stream)))
+
+    def launch(self, max_ctas=-1, stream=None):
+        """max_ctas -1: one workgroup per tile; 0: persistent, one resident grid;
+        > 0: persistent with at most that many workgroups."""
+        _check(lib().cb_batch_launch(ctypes.c_void_p(self.ws.data_ptr()), int(max_ctas), _stream(stream)))

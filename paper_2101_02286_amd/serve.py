@@ -245,7 +245,7 @@ class GpuExecutor:
             items[i].inp = f.data_ptr()
             items[i].out = out.data_ptr()
             keep.append(st)
-        need = cb.lib().cb_batch_workspace_size(len(reqs))
+        need = cb.lib().cb_batch_workspace_bytes(items, len(reqs))
         ws = self.ws.get(slot)
         if ws is None or ws.numel() < need:
             ws = torch.empty(max(need, 1 << 16), dtype=torch.uint8, device=self.device)

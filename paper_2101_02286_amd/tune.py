@@ -14,7 +14,14 @@ For one (bands, n, precision, grid shape, axis) it times every valid choice of
   * tile_order    -- strided lines: tiles in launch order or grouped by XCD,
 with HIP events on the launch stream, and returns the fastest.  Results are
 cached in a JSON file keyed by the problem so a process tunes once.
+
+tune_batch() tunes a batched launch as a whole: a batch runs one launch per
+kernel class, so a choice that is fastest for one item alone can split the
+batch into more classes and slow it down.  It starts from the automatic plans
+and, one group of items sharing a matrix and row layout at a time, keeps a
+choice only when the whole batch gets faster.
 """
+import collections
 import json
 import os
 
@@ -138,3 +145,97 @@ def tune(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, reps
 def tuned_plan(bands, n, f, axis, stencil=None, precision="fp64", refine_iters=0, **kw):
     best, _ = tune(bands, n, f, axis, stencil, precision, refine_iters, **kw)
     return cb.Plan(bands, n, precision=precision, refine_iters=refine_iters, **best)
+
+
+BATCH_ROWS = (4, 6, 8, 12, 16, 32)
+
+
+def batch_candidates(bands, n, precision, refine_iters=0, strided=False):
+    """Plan choices that change a batched launch of lines of n rows: rows per
+    lane, interior solve, and the lane exchanges (unit-stride rows) or the
+    tile order (strided rows).  Lines per workgroup and unit-stride staging
+    are the batch's own choice and are not searched."""
+    out = []
+    for rpl in BATCH_ROWS:
+        try:
+            cb.Plan(bands, n, precision=precision, refine_iters=refine_iters, rows_per_lane=rpl,
+                    host_only=True).close()
+        except cb.CbError:
+            continue
+        interiors = (2,) if rpl == 32 else ((1, 2) if rpl in (8, 12, 16) else (1,))
+        for it in interiors:
+            for v in ((1, 2) if strided else (0, 1)):
+                c = dict(rows_per_lane=rpl, interior=it)
+                c.update(dict(tile_order=v) if strided else dict(block_barriers=v))
+                out.append(c)
+    return out
+
+
+def tune_batch(items, precision="fp64", refine_iters=0, reps=5, max_ctas=-1, min_gain=0.02, stream=None,
+               max_candidates=None):
+    """Tune the plans of a batched launch by its whole-batch time.
+
+    items: (bands, stencil or None, f, out, axis) tuples; items with the same
+    bands, line length and row layout (unit stride or strided) share a plan
+    (a group).  Starting from the automatic plans, for each group in order of
+    decreasing unknowns, every choice of batch_candidates() is timed in the
+    whole batch (median of `reps` launches) and kept when it is faster than
+    the best so far by more than `min_gain`.
+
+    Returns (plans, choices, result): plans[i] is item i's plan (shared
+    objects within a group), choices maps a group's description to the plan
+    arguments kept ({} = automatic), and result holds the automatic and tuned
+    batch times in ms and the number of timed candidates."""
+    stream = stream or torch.cuda.current_stream()
+    groups = collections.OrderedDict()
+    for i, (bands, st, f, out, ax) in enumerate(items):
+        n = f.shape[2 - ax]
+        key = (tuple(float(b) for b in bands), n, f.stride(2 - ax) != 1)
+        groups.setdefault(key, []).append(i)
+
+    def make(key, kw):
+        return cb.Plan(list(key[0]), key[1], precision=precision, refine_iters=refine_iters, **kw)
+
+    plans = {k: make(k, {}) for k in groups}
+    choice = {k: {} for k in groups}
+    ws = [None]
+
+    def batch_ms(pl):
+        b = cb.Batch([(pl[k], items[i][1], items[i][2], items[i][3], items[i][4])
+                      for k, idx in groups.items() for i in idx], stream=stream, workspace=ws[0])
+        ws[0] = b.ws
+        return _time(lambda: b.launch(max_ctas, stream), reps, stream)
+
+    base = best = batch_ms(plans)
+    timed = 0
+    order = sorted(groups, key=lambda k: -sum(items[i][2].numel() for i in groups[k]))
+    for k in order:
+        cands = batch_candidates(list(k[0]), k[1], precision, refine_iters, strided=k[2])
+        if max_candidates:
+            cands = cands[:max_candidates]
+        for c in cands:
+            try:
+                p = make(k, c)
+            except cb.CbError:
+                continue
+            trial = dict(plans)
+            trial[k] = p
+            try:
+                ms = batch_ms(trial)
+            except cb.CbError:
+                p.close()
+                continue
+            timed += 1
+            if ms < best * (1.0 - min_gain):
+                plans[k].close()
+                plans[k], choice[k], best = p, c, ms
+            else:
+                p.close()
+    final = batch_ms(plans)
+    per_item = [None] * len(items)
+    for k, idx in groups.items():
+        for i in idx:
+            per_item[i] = plans[k]
+    desc = {"n%d %s r%d" % (k[1], "strided" if k[2] else "unit-stride", (len(k[0]) - 1) // 2): choice[k]
+            for k in groups}
+    return per_item, desc, {"automatic_ms": base, "tuned_ms": final, "candidates_timed": timed}

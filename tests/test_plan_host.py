@@ -433,3 +433,18 @@ def test_generalized_pcr_on_request_without_row_count(n):
     info = p.info()
     assert info["interior_elimination"] == 0 and info["interior_elimination_strided"] == 0
     assert info["rows_per_lane_strided"] <= 16
+
+
+def test_batch_tuner_candidates_are_valid_plans():
+    """Every choice the batch tuner would time builds a host-only plan, and
+    the strided and unit-stride sets differ only in the layout knob."""
+    from paper_2101_02286_amd import tune
+    tri = schemes.bands_collocated(schemes.DERIV6)
+    penta = schemes.bands_collocated(schemes.DERIV10)
+    for bands, n, prec in ((tri, 384, "fp32_refine"), (penta, 64, "fp64"), (tri, 1000, "fp64")):
+        for strided in (False, True):
+            cands = tune.batch_candidates(bands, n, prec, 0, strided)
+            assert cands
+            for c in cands:
+                assert ("tile_order" in c) == strided and ("block_barriers" in c) != strided
+                cb.Plan(bands, n, precision=prec, host_only=True, **c).close()
