@@ -523,12 +523,12 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
     a.band_rows = (p.desc.per_row || !p.desc.cyclic) ? 1 : 0;
   }
   a.wave_local = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 1 : 0;
-  a.fb = use_fb ? p.segdev + fbi : nullptr;
+  if (use_fb) a.fb = p.segdev_host[fbi];
   a.fb_type = use_fb ? (mode == MODE_S ? p.fb_type_s : p.fb_type_u) : 0;
-  // phase A: 256 threads; a unit-stride line per wavefront (consecutive rows
+  // phase A: 256 threads; unit-stride lines 16 lanes each (consecutive rows
   // in consecutive lanes), strided lines 64 adjacent ones per row access
   constexpr int kNTA = 256;
-  const int WA = mode == MODE_X ? kNTA / 64 : 64;
+  const int WA = mode == MODE_X ? kNTA / 16 : 64;
   const size_t sbytes = wg_scratch_bytes(p, g.nlines);
   void *scratch = nullptr;
   hipError_t e = hipSuccess;
@@ -551,7 +551,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   dim3 grid((unsigned)tiles, (unsigned)p.P);
   void *args[] = {&a};
   const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
-  const size_t lds_c = ((size_t)a.stage_off_c + (size_t)W * pitch) * sizeof(double);
+  const size_t lds_c = lds_c_of(NT);
   // FP64: phases A, B, C once.  FP32: the same with the interior solve in
   // FP32, then per refinement iteration the three phases on the residual,
   // phase C adding its correction to x

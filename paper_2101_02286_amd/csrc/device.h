@@ -133,6 +133,34 @@ __device__ __forceinline__ void stage_coef(const SegDev &sg, T *dst, int tid, in
   __syncthreads();
 }
 
+// One lane's block-PCR multipliers for the first TP levels of the reduced
+// system and its final solve, loaded ahead of the data they act on.  Lanes
+// whose multipliers differ (the full-block form) read them with vector loads;
+// inside the level loop each would wait for a memory round trip after the
+// exchange.  Levels >= TP (and plans with fewer levels) are not affected.
+template <typename T, int R, int TP>
+struct RedPre {
+  T mu[TP > 0 ? TP : 1][R * R], ml[TP > 0 ? TP : 1][R * R], w[R * R];
+};
+template <typename T, int R, int TP>
+__device__ __forceinline__ void red_prefetch(const SegDev &sg, int lr, RedPre<T, R, TP> &pre) {
+  constexpr int RR = R * R;
+  const T *rd = red_of<T>(sg);
+#pragma unroll
+  for (int t = 0; t < TP; ++t) {
+    const int tt = t < sg.Tred ? t : 0;  // levels the plan lacks are never used: stay in bounds
+    const T *mu = rd + ((size_t)(tt * sg.L + lr) * 2) * RR;
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+      pre.mu[t][i] = cld(mu + i);
+      pre.ml[t][i] = cld(mu + RR + i);
+    }
+  }
+  const T *w = wf_of<T>(sg) + (size_t)lr * RR;
+#pragma unroll
+  for (int i = 0; i < RR; ++i) pre.w[i] = cld(w + i);
+}
+
 // Solve the segment in place: on entry v[0..m) holds b of the lane's rows, on
 // exit x.  Padding slots (k >= m) hold zero and stay zero.  `cl` is the LDS
 // copy of the coefficient blocks when CSRC == CSRC_LDS.
@@ -141,9 +169,12 @@ __device__ __forceinline__ void stage_coef(const SegDev &sg, T *dst, int tid, in
 // are identity equations (x~ = b, its couplings to other lanes zero) and the
 // last lane has no forward coupling; the reduced-system multipliers are read
 // per lane.  Used for whole workgroup partitions (the full-block plans).
-template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL, bool ILU = false, bool UACYC = false>
+// `pre`: the lane's multipliers for the first TP levels, from red_prefetch.
+template <int R, int M, typename T, bool UNI, int CSRC = CSRC_GLOBAL, bool ILU = false, bool UACYC = false,
+          int TP = 0>
 __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const LanePos &p, int type,
-                                              int m, Xchg &xc, const T *cl = nullptr) {
+                                              int m, Xchg &xc, const T *cl = nullptr,
+                                              const RedPre<T, R, TP> *pre = nullptr) {
   constexpr int N = M - R;
   constexpr int TI = ceil_log2_c(N);
   constexpr int RR = R * R;
@@ -214,25 +245,32 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
   // ---- reduced cyclic block system across lanes: block PCR (Alg. 3) ----
   const T *rd = red_of<T>(sg);
   const int lr = (UNI && !UACYC) ? 0 : p.l;
-  for (int t = 0; t < sg.Tred; ++t) {
+  // one level: x~_l -= MU x~_{l+s} + ML x~_{l-s}, multipliers from mu(i), ml(i)
+  auto level = [&](int t, auto mu, auto ml) {
     const int s = 1 << t;
     xc.publish(p.tid, xt);
     T xp[R], xm[R];
     xc.fetch(p.tid_of((p.l + s) & (p.L - 1)), xp);
     xc.fetch(p.tid_of((p.l - s) & (p.L - 1)), xm);
     xc.done();
-    const T *mu = rd + ((size_t)(t * sg.L + lr) * 2) * RR;
-    const T *ml = mu + RR;
     T xn[R];
 #pragma unroll
     for (int a = 0; a < R; ++a) {
       T acc = xt[a];
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc -= cld(mu + a * R + c) * xp[c] + cld(ml + a * R + c) * xm[c];
+      for (int c = 0; c < R; ++c) acc -= mu(a * R + c) * xp[c] + ml(a * R + c) * xm[c];
       xn[a] = acc;
     }
 #pragma unroll
     for (int a = 0; a < R; ++a) xt[a] = xn[a];
+  };
+#pragma unroll
+  for (int t = 0; t < TP; ++t)
+    if (t < sg.Tred) level(t, [&](int i) { return pre->mu[t][i]; }, [&](int i) { return pre->ml[t][i]; });
+  for (int t = TP; t < sg.Tred; ++t) {
+    const T *mu = rd + ((size_t)(t * sg.L + lr) * 2) * RR;
+    const T *ml = mu + RR;
+    level(t, [&](int i) { return cld(mu + i); }, [&](int i) { return cld(ml + i); });
   }
   {
     const T *w = wf_of<T>(sg) + (size_t)lr * RR;
@@ -241,7 +279,7 @@ __device__ __forceinline__ void solve_segment(T (&v)[M], const SegDev &sg, const
     for (int a = 0; a < R; ++a) {
       T acc = (T)0;
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc += cld(w + a * R + c) * xt[c];
+      for (int c = 0; c < R; ++c) acc += (TP > 0 ? pre->w[a * R + c] : cld(w + a * R + c)) * xt[c];
       xn[a] = acc;
     }
 #pragma unroll

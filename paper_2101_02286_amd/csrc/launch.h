@@ -71,7 +71,9 @@ struct WgArgs {
                              // exchanges need only wavefront-local ordering)
   int sc_stride;             // scratch doubles per (line, partition): 3R, or 4R
                              // when refining (+ the current x at the interface rows)
-  const SegDev *fb;          // phase C on whole partitions: the full-block plan
+  SegDev fb;                 // phase C on whole partitions: the full-block plan,
+                             // by value so that its fields arrive with the
+                             // arguments (partition i starts at row i * fb.S)
   int fb_type;               // ... and its middle lanes' coefficient block
   int band_rows;             // FP64 residual: 1 reads bands per row, 0 band_c
   double band_c[2 * kMaxR + 1];  // constant bands a_{-R..R}

@@ -60,6 +60,20 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
   base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
 }
 
+// First row of workgroup partition i (i = P: n).  The full-block form has
+// equal partitions of fb.S rows, so no table is read.
+template <bool FB>
+__device__ __forceinline__ int64_t part_start(const WgArgs &a, int i) {
+  return FB ? (int64_t)i * a.fb.S : (int64_t)a.wg_start[i];
+}
+
+// Block-PCR levels whose multipliers the full-block form loads with the
+// data (tridiagonal: all levels of up to 64 lanes).
+template <int R, bool FB>
+constexpr int wg_red_prefetch() {
+  return FB && R == 1 ? 6 : 0;
+}
+
 // Solve the interior block D_i of workgroup partition `part` for the lane's
 // rows.  With xi/xi1 given (phase C), the right-hand side first loses the
 // couplings to the interface unknowns x~_i (first r rows of D_i) and
@@ -91,7 +105,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   // couplings of the block's end rows to the interface values, the
   // coefficient blocks) is issued together with the data, so the workgroup
   // waits for one round trip to memory instead of several in a row.
-  const SegDev &sg = FB ? *a.fb : a.segs[part];
+  const SegDev &sg = FB ? a.fb : a.segs[part];
   int type;
   if (FB) {
     start = p.l * M;
@@ -103,7 +117,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
   }
   const int S = sg.S;
   // first row of the block: D_i, or with FB the partition's first row
-  const int64_t seg0 = a.wg_start[part] + (FB ? 0 : R);
+  const int64_t seg0 = part_start<FB>(a, part) + (FB ? 0 : R);
   const int64_t row0 = seg0 + start;
   const bool staged = MODE == MODE_X && tb != nullptr;
   constexpr int QQ = Q > 0 ? Q : 1;
@@ -134,7 +148,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     if (Q > 0) {
 #pragma unroll
       for (int i = 0; i < QQ; ++i) {
-        int64_t r0 = seg0 - QQ + i, r1 = a.wg_start[part + 1] + i;
+        int64_t r0 = seg0 - QQ + i, r1 = part_start<FB>(a, part + 1) + i;
         r0 = r0 < 0 ? r0 + a.n : r0;
         r1 = r1 >= a.n ? r1 - a.n : r1;
         gp[i] = (active && p.l == 0) ? a.in[base + r0 * a.rs] : 0.0;
@@ -142,6 +156,9 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
       }
     }
   }
+  constexpr int TP = wg_red_prefetch<R, FB>();
+  RedPre<T, R, TP> pre;
+  if (TP > 0) red_prefetch<T, R, TP>(sg, p.l, pre);
   if (RES) {  // the current x of the lane's rows (written by the previous phase C)
     const double *xin = a.out + base + row0 * a.rs;
 #pragma unroll
@@ -249,7 +266,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
     }
   }
   if constexpr (FB) {
-    solve_segment<R, M, T, true, CSRC_GLOBAL, ILU, true>(v, sg, p, type, M, xc);
+    solve_segment<R, M, T, true, CSRC_GLOBAL, ILU, true, TP>(v, sg, p, type, M, xc, nullptr, &pre);
   } else if constexpr (sizeof(T) == sizeof(double)) {
     if (a.coef_lds)
       solve_segment<R, M, double, false, CSRC_LDS, ILU>(v, sg, p, type, m, xc, coef_lds);
@@ -283,15 +300,16 @@ constexpr int wg_max_threads() {
 // phase reads only those windows (and the interface rows), computing b on
 // the fly when the stencil is fused.  T threads share one (line, partition)
 // and take every T-th row of both windows, all loads issued before the
-// first product.  Unit-stride lines: one wavefront each (consecutive rows in
-// consecutive lanes), summed by a shuffle tree.  Strided lines: 4 threads
-// each, 64 adjacent lines per workgroup (one contiguous row segment per
-// access), summed through LDS.  Both sums run in a fixed order.
+// first product.  Unit-stride lines: 16 lanes each, 4 per wavefront
+// (consecutive rows in consecutive lanes, 128-byte segments; windows of up
+// to 80 rows in one round of loads), summed by a shuffle tree.  Strided
+// lines: 4 threads each, 64 adjacent lines per workgroup (one contiguous row
+// segment per access), summed through LDS.  Both sums run in a fixed order.
 template <int R, int MODE, int Q, bool RES = false>
 __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   extern __shared__ double smem[];
   constexpr int NTA = 256;
-  constexpr int T = MODE == MODE_X ? 64 : NTA / 64;
+  constexpr int T = MODE == MODE_X ? 16 : NTA / 64;
   constexpr int WA = NTA / T;  // lines per workgroup
   const int tid = threadIdx.x;
   const int li = MODE == MODE_X ? tid / T : tid % WA;
@@ -346,7 +364,7 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   for (int c = 0; c < R; ++c) yf[c] = yl[c] = 0.0;
   if (active) {
     // rows t, t+T, ... of the first window [0, K) and of the last [N-K, N)
-    constexpr int CH = MODE == MODE_X ? 2 : 12;  // rows per thread and window issued together
+    constexpr int CH = MODE == MODE_X ? 5 : 12;  // rows per thread and window issued together
     for (int j0 = 0; j0 < K; j0 += CH * T) {
       double bf[CH], bl[CH];
 #pragma unroll
@@ -370,9 +388,9 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
     }
   }
   if (MODE == MODE_X) {
-    // the wavefront's 64 partial sums, by a shuffle tree
+    // the T partial sums of the (line, partition), by a shuffle tree
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int off = T / 2; off >= 1; off >>= 1) {
 #pragma unroll
       for (int c = 0; c < R; ++c) {
         yf[c] += __shfl_xor(yf[c], off, 64);
@@ -524,7 +542,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] += xo[k];
   }
-  const int64_t seg0 = a.wg_start[part] + (FB ? 0 : R);
+  const int64_t seg0 = part_start<FB>(a, part) + (FB ? 0 : R);
   if (MODE == MODE_X && tb != nullptr) {
     // mirror of the staged load: every lane has finished reading the tile
     // (its stencil halo) before any lane overwrites it
@@ -533,7 +551,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
     for (int k = 0; k < M; ++k)
       if (k < m) tb[tile_at<M>(start + k)] = v[k];
     xc.sync();
-    const int S = FB ? a.fb->S : a.segs[part].S;
+    const int S = FB ? a.fb.S : a.segs[part].S;
     double *lout = a.out + base + seg0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
