@@ -452,7 +452,10 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   const int fbi = mode == MODE_S ? p.fb_seg_s : p.fb_seg_u;
   const bool use_fb = fbi >= 0 && !fp32 && k->fn_c_fb != nullptr && p.desc.x_staging != 1;
   const int L = use_fb ? p.segs[fbi].L : p.segs[so].L;
-  int NT = mode == MODE_X ? std::max(L, 256) : std::min(1024, 16 * L);
+  // unit-stride tiles: 2 lines of a full-block plan (measured fastest; more
+  // workgroups of fewer waves each), else 256 threads, which amortise the
+  // staging of per-partition coefficients; strided tiles: 16 lines
+  int NT = mode == MODE_X ? std::max(L, use_fb ? 128 : 256) : std::min(1024, 16 * L);
   if (p.desc.lines_per_wg > 0) NT = p.desc.lines_per_wg * L;
   NT = std::min(std::max(NT, L), k->max_threads);
   if (L > k->max_threads) return fail(CB_ERR_UNSUPPORTED, "partition needs too many lanes");
