@@ -476,9 +476,15 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   auto lds_c_of = [&](int nt) { return ((size_t)nt * 2 * RSw + extra + (size_t)(nt / L) * pitch) * 8; };
   // phase B: one thread per (line, partition), 256-thread blocks
   const int NTB = 256, WB = std::max(1, NTB / p.P);
-  const size_t lds_b = (size_t)2 * WB * p.P * p.R * sizeof(double);
+  const size_t lds_b0 = (size_t)2 * WB * p.P * p.R * sizeof(double);
+  const size_t nterms = p.prog.src.size();
+  const size_t lds_bp = lds_b0 + nterms * p.R * p.R * sizeof(double) +
+                        (p.prog.row_off.size() + nterms) * sizeof(int);
   const size_t cap = lds_cap();
-  if (lds_b > cap) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
+  if (lds_b0 > cap) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
+  // the program goes to LDS with the block's values when both fit
+  const bool prog_lds = lds_bp <= cap;
+  const size_t lds_b = prog_lds ? lds_bp : lds_b0;
   while (NT > L && lds_c_of(NT) > cap) NT /= 2;
   if (lds_c_of(NT) > cap) return fail(CB_ERR_UNSUPPORTED, "partition too long for one workgroup");
   const int W = NT / L;
@@ -514,6 +520,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.row_off = p.d_row_off;
   a.src = p.d_src;
   a.mats = p.d_mats;
+  a.nterms = (int)nterms;
+  a.prog_lds = prog_lds ? 1 : 0;
   a.bfun = p.d_bfun;
   a.kw = p.Kw;
   // scratch per (line, partition): b~, the two ends of y, and when refining

@@ -65,6 +65,8 @@ struct WgArgs {
   const double *LtUt;        // [P][2][R][R]
   const int *row_off, *src;  // reduced program
   const double *mats;
+  int nterms;                // its terms (src entries, R x R matrices)
+  int prog_lds;              // phase B copies the program to LDS first
   const double *bfun;        // [P][2][R][kw] boundary rows of D_i^{-1} (phase A)
   int kw;                    // their window length
   int wave_local;            // phase C: every line lies in one wavefront (its

@@ -434,7 +434,9 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
 // the scratch values of its partition and the previous one, then the
 // precomputed program of Algorithm 1 (block-PCR levels with detach/reattach
 // for any P, the final folded solve) runs in LDS; x~_i replaces b~_i in the
-// scratch array.
+// scratch array.  With a.prog_lds the program itself (its term ranges,
+// sources and matrices) is copied to LDS first, together with the scratch
+// reads, so the phases wait on no memory round trip.
 template <int R>
 __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
   extern __shared__ double smem[];
@@ -442,6 +444,19 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
   const int WB = NT / P > 0 ? NT / P : 1;  // lines per block
   double *cur = smem, *nxt = smem + (size_t)WB * P * R;
   const int64_t line0 = (int64_t)blockIdx.x * WB;
+  const int *prog_ro = a.row_off, *prog_src = a.src;
+  const double *prog_m = a.mats;
+  if (a.prog_lds) {
+    double *lm = smem + (size_t)2 * WB * P * R;
+    int *lro = reinterpret_cast<int *>(lm + (size_t)a.nterms * R * R);
+    int *lsrc = lro + (size_t)a.nphase * (P + 1);
+    for (int i = threadIdx.x; i < a.nterms * R * R; i += NT) lm[i] = a.mats[i];
+    for (int i = threadIdx.x; i < a.nphase * (P + 1); i += NT) lro[i] = a.row_off[i];
+    for (int i = threadIdx.x; i < a.nterms; i += NT) lsrc[i] = a.src[i];
+    prog_ro = lro;
+    prog_src = lsrc;
+    prog_m = lm;
+  }
   for (int idx = threadIdx.x; idx < WB * P; idx += NT) {
     const int li = idx / P, j = idx % P;
     const int64_t ln = line0 + li;
@@ -466,7 +481,7 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
   }
   __syncthreads();
   for (int ph = 0; ph < a.nphase; ++ph) {
-    const int *ro = a.row_off + ph * (P + 1);
+    const int *ro = prog_ro + ph * (P + 1);
     for (int idx = threadIdx.x; idx < WB * P; idx += NT) {
       const int li = idx / P, j = idx % P;
       const int t0 = ro[j], t1 = ro[j + 1];
@@ -478,8 +493,8 @@ __global__ __launch_bounds__(256) void k_wg_b(const WgArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         for (int t = t0; t < t1; ++t) {
-          const double *mt = a.mats + (size_t)t * R * R;
-          const double *xs = cur + (li * P + a.src[t]) * R;
+          const double *mt = prog_m + (size_t)t * R * R;
+          const double *xs = cur + (li * P + prog_src[t]) * R;
 #pragma unroll
           for (int r = 0; r < R; ++r)
 #pragma unroll
