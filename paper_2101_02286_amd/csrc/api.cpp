@@ -295,13 +295,20 @@ size_t batch_bytes(const cb_batch_item *items, int32_t n_items) {
 
 // Strided tiles in XCD-grouped order (workgroups are dealt to the XCDs in
 // turn, so in launch order neighbouring tiles run on different XCDs):
-// automatic when row segments are narrower than a 128-byte L2 line (its
-// tiles then share lines) or rows lie at most 64 KB apart (measured: 3-4 KB
-// row strides gain 4-10 %, 1.5-2 MB ones lose 4-10 % with wide segments).
+// automatic when neighbouring tiles share L2 lines -- row segments narrower
+// than a 128-byte line, or segments that are not whole aligned lines (the
+// tile width does not divide a plane's lines, or the plane pitch is not a
+// multiple of 128 bytes: measured +15-37 % for 200-960-row lines of ragged
+// planes) -- or when rows lie at most 64 KB apart (measured: 3-4 KB row
+// strides gain 4-10 %, 1.5-2 MB ones with whole aligned segments lose 4-10 %).
 // Returns the XCD count to group over, or 1 for launch order.
-int tile_xcds(const Plan &p, int mode, int W, int64_t rs) {
+int tile_xcds(const Plan &p, int mode, int W, const Geo &g) {
+  const int64_t seg = (int64_t)W * (int64_t)sizeof(double);
+  const bool whole = g.su == 1 && seg % 128 == 0 && (g.nlines <= g.nu || (g.nu % W == 0 &&
+                                                      (g.sv * (int64_t)sizeof(double)) % 128 == 0));
   const bool on = mode == MODE_S && (p.desc.tile_order == 2 ||
-                                     (p.desc.tile_order == 0 && (W * 8 < 128 || rs * (int64_t)sizeof(double) <= 65536)));
+                                     (p.desc.tile_order == 0 &&
+                                      (!whole || g.rs * (int64_t)sizeof(double) <= 65536)));
   return on ? xcd_count() : 1;
 }
 
@@ -423,7 +430,7 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   const size_t lds = lds_of(W);
   const int64_t blocks = (g.nlines + W - 1) / W;
   if (blocks > 0x7fffffff) return fail(CB_ERR_UNSUPPORTED, "too many lines for one launch");
-  a.xcds = tile_xcds(p, mode, W, g.rs);
+  a.xcds = tile_xcds(p, mode, W, g);
   void *args[] = {&a};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(NT), args, lds, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -862,7 +869,7 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
     a.nudiv = make_divmagic((uint32_t)g.nu);
     a.lgL = ilog2(L);
     a.lgW = ilog2(W);
-    a.xcds = tile_xcds(p, mode, W, g.rs);  // used by one-workgroup-per-tile launches
+    a.xcds = tile_xcds(p, mode, W, g);  // used by one-workgroup-per-tile launches
     // lanes of a unit-stride line are adjacent threads: with L <= 64 a line
     // lies in one wavefront and its exchanges need no workgroup barrier
     a.block_sync = (mode == MODE_X && L <= 64 && 64 % L == 0 && p.desc.block_barriers == 0) ? 0 : 1;
