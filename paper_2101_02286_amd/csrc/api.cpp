@@ -489,7 +489,9 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
                         (p.prog.row_off.size() + nterms) * sizeof(int);
   const size_t cap = lds_cap();
   if (lds_b0 > cap) return fail(CB_ERR_UNSUPPORTED, "too many partitions for the reduced solve");
-  // the program goes to LDS with the block's values when both fit
+  // the program goes to LDS with the block's values when both fit (always on
+  // gfx950 for P <= 64 and r <= 3: at most 104 KB of its 160 KB; the reads
+  // from memory remain for a device that reports less)
   const bool prog_lds = lds_bp <= cap;
   const size_t lds_b = prog_lds ? lds_bp : lds_b0;
   while (NT > L && lds_c_of(NT) > cap) NT /= 2;
