@@ -68,10 +68,12 @@ __device__ __forceinline__ int64_t part_start(const WgArgs &a, int i) {
 }
 
 // Block-PCR levels whose multipliers the full-block form loads with the
-// data (tridiagonal: all levels of up to 64 lanes).
-template <int R, bool FB>
+// data: tridiagonal partitions of up to 512 rows, log2(512 / M) levels (a
+// level more costs registers for nothing: 16-row lanes take 71 VGPRs with 5
+// levels, 85 with 6).
+template <int R, int M, bool FB>
 constexpr int wg_red_prefetch() {
-  return FB && R == 1 ? 6 : 0;
+  return FB && R == 1 ? ceil_log2_c(512 / M) : 0;
 }
 
 // Solve the interior block D_i of workgroup partition `part` for the lane's
@@ -156,7 +158,7 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
       }
     }
   }
-  constexpr int TP = wg_red_prefetch<R, FB>();
+  constexpr int TP = wg_red_prefetch<R, M, FB>();
   RedPre<T, R, TP> pre;
   if (TP > 0) red_prefetch<T, R, TP>(sg, p.l, pre);
   if (RES) {  // the current x of the lane's rows (written by the previous phase C)
