@@ -344,6 +344,30 @@ def test_full_block_phase_c(gpu, P, axis, bands):
     assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
 
 
+@pytest.mark.parametrize("rows", [128, 256, 1024, 2048])
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+def test_full_block_partition_sizes(gpu, rows, axis, bands):
+    """Full-block phase C on partitions shorter and longer than 512 rows: its
+    tridiagonal lanes load the first block-PCR levels' multipliers with the
+    data (levels a short partition lacks are never used, a long one's later
+    levels are read in the level loop), on 1-2 lines per workgroup."""
+    bd, sch = dict(tri=(TRI, schemes.DERIV6), penta=(PENTA, schemes.DERIV10))[bands]
+    P = 4
+    n = rows * P
+    shape = shape_with(axis, n, (3, 7))
+    plan = cb.Plan(bd, n, partitions=P)
+    info = plan.info()
+    assert info["fullblock_seg" if axis == 0 else "fullblock_seg_strided"] >= 0
+    b = synth.random_uniform(shape, seed=rows + axis)
+    x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+    assert relerr(x, oracle.solve_axis(b.numpy(), axis, bd)) <= 1e-12
+    f, _ = synth.random_modes(shape, seed=rows)
+    lo, c = deriv_stencil(sch, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192
