@@ -79,7 +79,12 @@ __device__ __forceinline__ void line_tile(const LineArgs &a, int64_t tile, doubl
   }
   const int64_t rs = MODE == MODE_X ? 1 : a.rs;
   const double *in = a.in + base + start * rs;
-  double *out = a.out + base + start * rs;
+  // 32-row strided lanes: the output row as a uniform distance from the input
+  // row, so only one address stays live through the solve (that instance
+  // otherwise spills two 8-byte values per thread; the others spill more
+  // with this form)
+  double *out = (MODE == MODE_S && M == 32) ? const_cast<double *>(in) + (a.out - a.in)
+                                            : a.out + base + start * rs;
 
   // MODE_X: a lane's rows are one contiguous 8M-byte run, so one vector load
   // instruction touches many cache lines partially; these loads go through
