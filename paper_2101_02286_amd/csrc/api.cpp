@@ -568,7 +568,14 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.scratch = static_cast<double *>(scratch);
   const int64_t tiles = (g.nlines + W - 1) / W;
   const int64_t tiles_a = (g.nlines + WA - 1) / WA;
-  dim3 grid((unsigned)tiles, (unsigned)p.P);
+  // unit-stride lines: 1D grids with the partition varying fastest (tile *
+  // P + part); strided lines: (tile, part)
+  if (mode == MODE_X && std::max(tiles, tiles_a) * p.P >= (int64_t(1) << 31)) {
+    if (!fs) (void)hipFreeAsync(scratch, stream);
+    return fail(CB_ERR_UNSUPPORTED, "too many line tiles times partitions for one launch");
+  }
+  const dim3 grid = mode == MODE_X ? dim3((unsigned)(tiles * p.P)) : dim3((unsigned)tiles, (unsigned)p.P);
+  const dim3 grid_a = mode == MODE_X ? dim3((unsigned)(tiles_a * p.P)) : dim3((unsigned)tiles_a, (unsigned)p.P);
   void *args[] = {&a};
   const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
   const size_t lds_c = lds_c_of(NT);
@@ -578,7 +585,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   for (int it = 0; it <= iters && e == hipSuccess; ++it) {
     const void *fa = it == 0 ? k->fn_a : k->fn_a_res;
     const void *fc = !fp32 ? (use_fb ? k->fn_c_fb : k->fn_c) : (it == 0 ? k->fn_c32 : k->fn_c32_res);
-    e = hipLaunchKernel(fa, dim3((unsigned)tiles_a, (unsigned)p.P), dim3(kNTA), args, lds_a, stream);
+    e = hipLaunchKernel(fa, grid_a, dim3(kNTA), args, lds_a, stream);
     if (e == hipSuccess)
       e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
     if (e == hipSuccess) e = hipLaunchKernel(fc, grid, dim3(NT), args, lds_c, stream);

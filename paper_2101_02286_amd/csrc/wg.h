@@ -37,7 +37,7 @@ __device__ __forceinline__ double wg_band(const WgArgs &a, int64_t g, int o) {
 }
 
 template <int R, int M, int MODE>
-__device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &line, bool &active,
+__device__ __forceinline__ void wg_setup(const WgArgs &a, int64_t tile, LanePos &p, int64_t &line, bool &active,
                                          int64_t &base) {
   p.tid = threadIdx.x;
   p.lgL = a.lgL;
@@ -52,12 +52,29 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, LanePos &p, int64_t &l
     p.l = p.tid >> p.lgW;
     p.li = p.tid & (p.W - 1);
   }
-  line = (int64_t)blockIdx.x * p.W + p.li;
+  line = tile * p.W + p.li;
   active = line < a.nlines;
   const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
   const uint32_t line32 = active ? (uint32_t)line : 0u;
   const uint32_t lv = fd.div(line32), lu = line32 - lv * a.nudiv.d;
   base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
+}
+
+// Workgroup -> (line tile, partition).  Unit-stride lines: a 1D grid with the
+// partition varying fastest, so workgroups dispatched together read one
+// line's partitions one after the other (contiguous memory) rather than the
+// same partition of lines 64 KB apart; strided lines: a 2D grid (tile, part)
+// with the tile varying fastest, so neighbouring tiles' row segments, which
+// share DRAM pages, are read together.
+template <int MODE>
+__device__ __forceinline__ void wg_block(int P, int64_t &tile, int &part) {
+  if (MODE == MODE_X) {
+    part = (int)(blockIdx.x % (unsigned)P);
+    tile = blockIdx.x / (unsigned)P;
+  } else {
+    part = blockIdx.y;
+    tile = blockIdx.x;
+  }
 }
 
 // First row of workgroup partition i (i = P: n).  The full-block form has
@@ -316,8 +333,10 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   const int tid = threadIdx.x;
   const int li = MODE == MODE_X ? tid / T : tid % WA;
   const int t = MODE == MODE_X ? tid % T : tid / WA;
-  const int part = blockIdx.y;
-  const int64_t line = (int64_t)blockIdx.x * WA + li;
+  int part;
+  int64_t tile;
+  wg_block<MODE>(a.P, tile, part);
+  const int64_t line = tile * WA + li;
   const bool active = line < a.nlines;
   const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
   const uint32_t line32 = active ? (uint32_t)line : 0u;
@@ -534,8 +553,11 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
   LanePos p;
   int64_t line, base;
   bool active;
-  wg_setup<R, M, MODE>(a, p, line, active, base);
-  const int P = a.P, part = blockIdx.y, NT = blockDim.x;
+  int part;
+  int64_t tile;
+  wg_block<MODE>(a.P, tile, part);
+  wg_setup<R, M, MODE>(a, tile, p, line, active, base);
+  const int P = a.P, NT = blockDim.x;
   double xi[R], xi1[R], xif0[R], xif1[R];
   {
     const int64_t ln = active ? line : 0;
