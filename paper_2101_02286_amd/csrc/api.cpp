@@ -568,14 +568,21 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.scratch = static_cast<double *>(scratch);
   const int64_t tiles = (g.nlines + W - 1) / W;
   const int64_t tiles_a = (g.nlines + WA - 1) / WA;
-  // unit-stride lines: 1D grids with the partition varying fastest (tile *
-  // P + part); strided lines: (tile, part)
-  if (mode == MODE_X && std::max(tiles, tiles_a) * p.P >= (int64_t(1) << 31)) {
+  // 1D grids with the partition varying fastest (tile * P + part), except for
+  // strided lines that form one contiguous run of memory across planes (a
+  // C-order array along z): there consecutive tiles of the same partition
+  // read contiguous row segments, and the grid is (tile, part), the tile
+  // fastest.  Measured at n = 8192, P = 16: y (row strides 0.5-8 KB) 3-4 %
+  // faster partition-fastest, z 3-14 % faster tile-fastest
+  const bool contiguous_lines = g.su == 1 && (g.nlines <= g.nu || g.sv == g.nu);
+  const bool part_fast = g.rs == 1 || !contiguous_lines;
+  if (part_fast && std::max(tiles, tiles_a) * p.P >= (int64_t(1) << 31)) {
     if (!fs) (void)hipFreeAsync(scratch, stream);
     return fail(CB_ERR_UNSUPPORTED, "too many line tiles times partitions for one launch");
   }
-  const dim3 grid = mode == MODE_X ? dim3((unsigned)(tiles * p.P)) : dim3((unsigned)tiles, (unsigned)p.P);
-  const dim3 grid_a = mode == MODE_X ? dim3((unsigned)(tiles_a * p.P)) : dim3((unsigned)tiles_a, (unsigned)p.P);
+  a.part_fast = part_fast ? 1 : 0;
+  const dim3 grid = part_fast ? dim3((unsigned)(tiles * p.P)) : dim3((unsigned)tiles, (unsigned)p.P);
+  const dim3 grid_a = part_fast ? dim3((unsigned)(tiles_a * p.P)) : dim3((unsigned)tiles_a, (unsigned)p.P);
   void *args[] = {&a};
   const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
   const size_t lds_c = lds_c_of(NT);

@@ -77,6 +77,7 @@ struct WgArgs {
                              // by value so that its fields arrive with the
                              // arguments (partition i starts at row i * fb.S)
   int fb_type;               // ... and its middle lanes' coefficient block
+  int part_fast;             // phases A and C: 1D grid, partition fastest
   int band_rows;             // FP64 residual: 1 reads bands per row, 0 band_c
   double band_c[2 * kMaxR + 1];  // constant bands a_{-R..R}
 };

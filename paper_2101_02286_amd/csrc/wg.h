@@ -60,17 +60,17 @@ __device__ __forceinline__ void wg_setup(const WgArgs &a, int64_t tile, LanePos 
   base = (int64_t)lu * a.su + (int64_t)lv * a.sv;
 }
 
-// Workgroup -> (line tile, partition).  Unit-stride lines: a 1D grid with the
+// Workgroup -> (line tile, partition).  a.part_fast: a 1D grid with the
 // partition varying fastest, so workgroups dispatched together read one
-// line's partitions one after the other (contiguous memory) rather than the
-// same partition of lines 64 KB apart; strided lines: a 2D grid (tile, part)
-// with the tile varying fastest, so neighbouring tiles' row segments, which
-// share DRAM pages, are read together.
-template <int MODE>
-__device__ __forceinline__ void wg_block(int P, int64_t &tile, int &part) {
-  if (MODE == MODE_X) {
-    part = (int)(blockIdx.x % (unsigned)P);
-    tile = blockIdx.x / (unsigned)P;
+// line's partitions one after the other (contiguous memory for unit-stride
+// lines: x 249 -> 270 GDOF/s at n = 8192, P = 16; y 3-4 % faster); else a 2D
+// grid (tile, part) with the tile varying fastest, for strided lines that
+// form one contiguous run across planes (z of a C-order array), whose
+// consecutive tiles then read contiguous row segments (3-14 % faster).
+__device__ __forceinline__ void wg_block(const WgArgs &a, int64_t &tile, int &part) {
+  if (a.part_fast) {
+    part = (int)(blockIdx.x % (unsigned)a.P);
+    tile = blockIdx.x / (unsigned)a.P;
   } else {
     part = blockIdx.y;
     tile = blockIdx.x;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   const int t = MODE == MODE_X ? tid % T : tid / WA;
   int part;
   int64_t tile;
-  wg_block<MODE>(a.P, tile, part);
+  wg_block(a, tile, part);
   const int64_t line = tile * WA + li;
   const bool active = line < a.nlines;
   const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
@@ -555,7 +555,7 @@ __global__ __launch_bounds__((wg_max_threads<M, MODE>())) void k_wg_c(const WgAr
   bool active;
   int part;
   int64_t tile;
-  wg_block<MODE>(a.P, tile, part);
+  wg_block(a, tile, part);
   wg_setup<R, M, MODE>(a, tile, p, line, active, base);
   const int P = a.P, NT = blockDim.x;
   double xi[R], xi1[R], xif0[R], xif1[R];
