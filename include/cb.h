@@ -160,7 +160,16 @@ cb_status cb_rhs_stencil(const cb_stencil *stencil, const cb_grid *grid, int32_t
 
 /* x = A^{-1} b along `axis` for every line of the grid (Sec. 4, Algorithm 1
  * applied to all lines at once).  b == x is allowed (in place); other
- * overlaps are not. */
+ * overlaps are not.  Lines split over P > 1 workgroups (also strided
+ * launches of FP64 one-partition plans with n > 4096) need a partition
+ * scratch of 3r doubles (4r when refining) per line and partition: the plan
+ * keeps one buffer per stream it is used on (calls on one stream are
+ * ordered by it, calls on different streams use different buffers),
+ * allocated by the first such call on a stream and grown (hipMalloc, after
+ * synchronizing that stream) when a call needs more; after 16 streams the
+ * device is synchronized and the buffers are released; cb_plan_destroy frees
+ * them.  While the stream is being captured into a graph the scratch is a
+ * stream-ordered allocation instead (hipMallocAsync / hipFreeAsync). */
 cb_status cb_solve(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b,
                    double *x, void *stream);
 
@@ -175,10 +184,10 @@ cb_status cb_apply_derivative(cb_plan_t plan, const cb_stencil *stencil, const c
 
 /* cb_solve for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.
- * Same arguments, checks and results (bitwise) as cb_solve, which takes a
- * stream-ordered allocation for the partition scratch of lines split over
- * P > 1 workgroups (also strided launches of FP64 one-partition plans with
- * n > 4096): 3r doubles per line and partition.  This variant uses instead a
+ * Same arguments, checks and results (bitwise) as cb_solve, which may
+ * allocate the partition scratch of lines split over P > 1 workgroups (also
+ * strided launches of FP64 one-partition plans with n > 4096): 3r doubles
+ * per line and partition.  This variant uses instead a
  * fixed array of CB_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
  * held until the process ends, and never calls hipMalloc, hipFree or any
  * other allocating routine.  A solve that would need more scratch (lines x

@@ -58,6 +58,9 @@ std::map<void *, BatchState> g_batch;
 // workspaces remembered before finished ones are forgotten
 constexpr size_t kBatchKeep = 256;
 
+// streams a plan keeps partition scratch for before it drops them all
+constexpr size_t kKeptScratchStreams = 16;
+
 // batch workspace layout: kBatchHdrBytes per class header (at most one class
 // per item), then the work table from a 256-byte boundary
 constexpr size_t kBatchHdrBytes = 64;
@@ -550,22 +553,6 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   constexpr int kNTA = 256;
   const int WA = mode == MODE_X ? kNTA / 16 : 64;
   const size_t sbytes = wg_scratch_bytes(p, g.nlines);
-  void *scratch = nullptr;
-  hipError_t e = hipSuccess;
-  if (fs) {
-    if (sbytes > fs->bytes)
-      return fail(CB_ERR_UNSUPPORTED, "this solve needs " + std::to_string(sbytes) +
-                                          " bytes of partition scratch, more than the " + std::to_string(fs->bytes) +
-                                          " bytes of the fixed buffer");
-    scratch = fs->ptr;
-  } else {
-    e = hipMallocAsync(&scratch, std::max<size_t>(sbytes, 256), stream);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
-    }
-  }
-  a.scratch = static_cast<double *>(scratch);
   const int64_t tiles = (g.nlines + W - 1) / W;
   const int64_t tiles_a = (g.nlines + WA - 1) / WA;
   // 1D grids with the partition varying fastest (tile * P + part), except for
@@ -576,10 +563,63 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // faster partition-fastest, z 3-14 % faster tile-fastest
   const bool contiguous_lines = g.su == 1 && (g.nlines <= g.nu || g.sv == g.nu);
   const bool part_fast = g.rs == 1 || !contiguous_lines;
-  if (part_fast && std::max(tiles, tiles_a) * p.P >= (int64_t(1) << 31)) {
-    if (!fs) (void)hipFreeAsync(scratch, stream);
+  if (part_fast && std::max(tiles, tiles_a) * p.P >= (int64_t(1) << 31))
     return fail(CB_ERR_UNSUPPORTED, "too many line tiles times partitions for one launch");
+  // Partition scratch: the caller's fixed buffer; else the plan's buffer
+  // for this stream (grown on demand); while the stream is being captured
+  // into a graph, a stream-ordered allocation (a graph memory node)
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  if (!fs && hipStreamIsCapturing(stream, &capst) != hipSuccess) {
+    (void)hipGetLastError();
+    capst = hipStreamCaptureStatusNone;
   }
+  const bool kept = !fs && capst == hipStreamCaptureStatusNone;
+  void *scratch = nullptr;
+  hipError_t e = hipSuccess;
+  if (fs) {
+    if (sbytes > fs->bytes)
+      return fail(CB_ERR_UNSUPPORTED, "this solve needs " + std::to_string(sbytes) +
+                                          " bytes of partition scratch, more than the " + std::to_string(fs->bytes) +
+                                          " bytes of the fixed buffer");
+    scratch = fs->ptr;
+  } else if (kept) {
+    ScratchCache &c = *p.sc;
+    std::lock_guard<std::mutex> lk(c.mu);
+    void *key = static_cast<void *>(stream);
+    if (!c.bufs.count(key) && c.bufs.size() >= kKeptScratchStreams) {
+      // many streams: wait for the device, then drop every kept buffer
+      e = hipDeviceSynchronize();
+      for (auto &kv : c.bufs)
+        if (e == hipSuccess && kv.second.first) e = hipFree(kv.second.first);
+      c.bufs.clear();
+      if (e != hipSuccess) return hip_fail(e, "cb_solve: releasing partition scratch");
+    }
+    std::pair<void *, size_t> &buf = c.bufs[key];
+    if (buf.second < sbytes) {  // grow: after this stream's earlier use of the buffer
+      if (buf.first) {
+        e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = hipFree(buf.first);
+        buf = {nullptr, 0};
+        if (e != hipSuccess) return hip_fail(e, "cb_solve: releasing partition scratch");
+      }
+      const size_t want = std::max<size_t>(sbytes, 256);
+      e = hipMalloc(&buf.first, want);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.bufs.erase(key);
+        return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
+      }
+      buf.second = want;
+    }
+    scratch = buf.first;
+  } else {
+    e = hipMallocAsync(&scratch, std::max<size_t>(sbytes, 256), stream);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CB_ERR_OOM, "cb_solve: scratch allocation failed");
+    }
+  }
+  a.scratch = static_cast<double *>(scratch);
   a.part_fast = part_fast ? 1 : 0;
   const dim3 grid = part_fast ? dim3((unsigned)(tiles * p.P)) : dim3((unsigned)tiles, (unsigned)p.P);
   const dim3 grid_a = part_fast ? dim3((unsigned)(tiles_a * p.P)) : dim3((unsigned)tiles_a, (unsigned)p.P);
@@ -597,7 +637,7 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
       e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);
     if (e == hipSuccess) e = hipLaunchKernel(fc, grid, dim3(NT), args, lds_c, stream);
   }
-  const hipError_t e2 = fs ? hipSuccess : hipFreeAsync(scratch, stream);
+  const hipError_t e2 = (fs || kept) ? hipSuccess : hipFreeAsync(scratch, stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
   return CB_OK;
@@ -673,6 +713,17 @@ cb_status cb_plan(const cb_plan_desc *desc, cb_plan_t *out) {
 cb_status cb_plan_destroy(cb_plan_t plan) {
   if (!plan) return CB_OK;
   cb_status s = CB_OK;
+  // the partition scratch the plan (and its strided partitioned form) kept
+  // per stream (hipFree waits for work still using it)
+  for (cb::Plan *q : {&plan->p, plan->p.strided_wg.get()}) {
+    if (!q || !q->sc) continue;
+    std::lock_guard<std::mutex> lk(q->sc->mu);
+    for (auto &kv : q->sc->bufs) {
+      const hipError_t e = kv.second.first ? hipFree(kv.second.first) : hipSuccess;
+      if (e != hipSuccess) s = hip_fail(e, "cb_plan_destroy: partition scratch");
+    }
+    q->sc->bufs.clear();
+  }
   if (plan->p.strided_wg && plan->p.strided_wg->dev_base) {
     hipError_t e = hipFree(plan->p.strided_wg->dev_base);
     if (e != hipSuccess) s = hip_fail(e, "cb_plan_destroy: hipFree");

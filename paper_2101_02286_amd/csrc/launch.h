@@ -135,8 +135,9 @@ struct FixedScratch {
   size_t bytes;
 };
 
-// cb_solve with the partition scratch in `fs` (NULL: a stream-ordered
-// allocation per launch), and the error reporting of the C ABI
+// cb_solve with the partition scratch in `fs` (NULL: the plan's kept
+// buffer, or under graph capture a stream-ordered allocation), and the
+// error reporting of the C ABI
 // (cb_last_error's message).
 cb_status solve_entry(cb_plan_t plan, const cb_grid *grid, int32_t axis, const double *b, double *x, void *stream,
                       const FixedScratch *fs);

@@ -3,7 +3,9 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/cb.h"
@@ -92,6 +94,15 @@ struct SegDev {
   const float *coef32, *red32, *wf32;
 };
 
+// Partition scratch a plan keeps for cb_solve (P > 1): one device buffer
+// per stream the plan is used on (calls on one stream are ordered by the
+// stream, calls on different streams use different buffers), grown on
+// demand.  Keys and values are a hipStream_t and device pointers.
+struct ScratchCache {
+  std::mutex mu;
+  std::map<void *, std::pair<void *, size_t>> bufs;
+};
+
 struct Plan {
   cb_plan_desc desc{};
   std::vector<double> bands;  // n*(2r+1) (expanded when per_row = 0)
@@ -141,6 +152,7 @@ struct Plan {
   // the same matrix split into workgroup partitions of about 1024 rows, since
   // a whole line per workgroup would leave room for only a few adjacent lines
   std::shared_ptr<Plan> strided_wg;
+  std::shared_ptr<ScratchCache> sc = std::make_shared<ScratchCache>();
 };
 
 // Builds the host-side factorisation.  Returns CB_OK or an error with msg.

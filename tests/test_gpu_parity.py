@@ -368,6 +368,31 @@ def test_full_block_partition_sizes(gpu, rows, axis, bands):
     assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
 
 
+def test_partitioned_scratch_kept_by_the_plan(gpu):
+    """cb_solve with P > 1 keeps its partition scratch in the plan, one buffer
+    per stream: a larger call after a smaller one grows it, and calls
+    alternating between two streams, which may overlap on the GPU, each use
+    their own stream's buffer (all results exact)."""
+    n, P = 1024, 8
+    plan = cb.Plan(TRI, n, partitions=P)
+    for other in ((2, 3), (40, 30), (2, 3)):
+        b = synth.random_uniform(shape_with(0, n, other), seed=other[0])
+        x = cb.solve(plan, b.to(gpu), 0).cpu().numpy()
+        assert relerr(x, oracle.solve_axis(b.numpy(), 0, TRI)) <= 1e-12
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    bs = [synth.random_uniform(shape_with(1, n, (16, 8 + i)), seed=10 + i) for i in range(6)]
+    bd = [b.to(gpu) for b in bs]
+    outs = [torch.full_like(b, float("nan")) for b in bd]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    for i in range(6):
+        cb.solve(plan, bd[i], 1, out=outs[i], stream=streams[i % 2])
+    torch.cuda.synchronize()
+    for b, o in zip(bs, outs):
+        assert relerr(o.cpu().numpy(), oracle.solve_axis(b.numpy(), 1, TRI)) <= 1e-12
+    plan.close()
+
+
 def test_c3a_two_level_full_size(gpu):
     """64x64 lines of n = 8192 split into P = 16 workgroup partitions."""
     n = 8192
