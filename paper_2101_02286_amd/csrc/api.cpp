@@ -622,7 +622,10 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   a.scratch = static_cast<double *>(scratch);
   a.part_fast = part_fast ? 1 : 0;
   const dim3 grid = part_fast ? dim3((unsigned)(tiles * p.P)) : dim3((unsigned)tiles, (unsigned)p.P);
-  const dim3 grid_a = part_fast ? dim3((unsigned)(tiles_a * p.P)) : dim3((unsigned)tiles_a, (unsigned)p.P);
+  // (unit-stride phase A: WA consecutive (line, partition) pairs per workgroup)
+  const dim3 grid_a = mode == MODE_X ? dim3((unsigned)((g.nlines * p.P + WA - 1) / WA))
+                      : part_fast    ? dim3((unsigned)(tiles_a * p.P))
+                                     : dim3((unsigned)tiles_a, (unsigned)p.P);
   void *args[] = {&a};
   const size_t lds_a = mode == MODE_X ? 0 : (size_t)kNTA * 2 * p.R * sizeof(double);
   const size_t lds_c = lds_c_of(NT);

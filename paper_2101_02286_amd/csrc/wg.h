@@ -321,7 +321,8 @@ constexpr int wg_max_threads() {
 // and take every T-th row of both windows, all loads issued before the
 // first product.  Unit-stride lines: 16 lanes each, 4 per wavefront
 // (consecutive rows in consecutive lanes, 128-byte segments; windows of up
-// to 80 rows in one round of loads), summed by a shuffle tree.  Strided
+// to 80 rows in one round of loads), consecutive pairs the partitions of one
+// line, summed by a shuffle tree.  Strided
 // lines: 4 threads each, 64 adjacent lines per workgroup (one contiguous row
 // segment per access), summed through LDS.  Both sums run in a fixed order.
 template <int R, int MODE, int Q, bool RES = false>
@@ -334,9 +335,19 @@ __global__ __launch_bounds__(256) void k_wg_a(const WgArgs a) {
   const int li = MODE == MODE_X ? tid / T : tid % WA;
   const int t = MODE == MODE_X ? tid % T : tid / WA;
   int part;
-  int64_t tile;
-  wg_block(a, tile, part);
-  const int64_t line = tile * WA + li;
+  int64_t line;
+  if (MODE == MODE_X) {
+    // WA (line, partition) pairs per workgroup, the partition varying
+    // fastest: neighbouring pairs read adjacent windows (the last one of
+    // partition i, the interface rows and the first window of i + 1)
+    const int64_t pair = (int64_t)blockIdx.x * WA + li;
+    line = pair / a.P;
+    part = (int)(pair - line * a.P);
+  } else {
+    int64_t tile;
+    wg_block(a, tile, part);
+    line = tile * WA + li;
+  }
   const bool active = line < a.nlines;
   const FastDiv fd{a.nudiv.d, a.nudiv.mul, a.nudiv.s1, a.nudiv.s2};
   const uint32_t line32 = active ? (uint32_t)line : 0u;
