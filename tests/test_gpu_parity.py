@@ -390,6 +390,19 @@ def test_partitioned_scratch_kept_by_the_plan(gpu):
     torch.cuda.synchronize()
     for b, o in zip(bs, outs):
         assert relerr(o.cpu().numpy(), oracle.solve_axis(b.numpy(), 1, TRI)) <= 1e-12
+    # more streams than the plan keeps buffers for: it waits for the device
+    # and releases them, then goes on allocating
+    many = [torch.cuda.Stream() for _ in range(18)]
+    b = synth.random_uniform(shape_with(2, n, (6, 5)), seed=99)
+    ref = oracle.solve_axis(b.numpy(), 2, TRI)
+    bd = b.to(gpu)
+    outs = [torch.full_like(bd, float("nan")) for _ in many]
+    for s, o in zip(many, outs):
+        s.wait_stream(torch.cuda.current_stream())
+        cb.solve(plan, bd, 2, out=o, stream=s)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert relerr(o.cpu().numpy(), ref) <= 1e-12
     plan.close()
 
 
