@@ -310,6 +310,7 @@ def leg_two_level(steps, warmup):
     res = {}
     n, P = 8192, 16
     plan = cb.Plan(bands, n, partitions=P)
+    plan32 = cb.Plan(bands, n, partitions=P, precision="fp32_refine")
     for ax in range(3):
         dims = [64, 64]
         dims.insert(ax, n)
@@ -317,7 +318,16 @@ def leg_two_level(steps, warmup):
         x = torch.empty_like(b)
         ms = _median_ms(lambda: cb.solve(plan, b, ax, out=x, stream=stream), steps, warmup, stream)
         res["n8192_P16_" + "xyz"[ax]] = {"ms": round(ms, 4), "gdofs": round(b.numel() / (ms * 1e-3) / 1e9, 2)}
+        if ax == 0:  # FP32 + refinement (automatic count) on the same lines, against the FP64 result
+            x32 = torch.empty_like(b)
+            ms32 = _median_ms(lambda: cb.solve(plan32, b, ax, out=x32, stream=stream), steps, warmup, stream)
+            torch.cuda.synchronize()
+            res["n8192_P16_x_fp32_refine"] = {
+                "ms": round(ms32, 4), "gdofs": round(b.numel() / (ms32 * 1e-3) / 1e9, 2),
+                "refine_iters": plan32.info()["refine_iters"],
+                "max_rel_diff_vs_fp64": float(((x32 - x).abs().max() / x.abs().max()).item())}
     plan.close()
+    plan32.close()
     scal = {}
     for P in (16, 15, 8, 7):
         n = 512 * P
