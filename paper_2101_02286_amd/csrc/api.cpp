@@ -460,7 +460,8 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // FP64 phase C on whole partitions when the plan has a full-block plan for
   // this layout (equal partitions of L*M rows, constant bands)
   const int fbi = mode == MODE_S ? p.fb_seg_s : p.fb_seg_u;
-  const bool use_fb = fbi >= 0 && !fp32 && k->fn_c_fb != nullptr && p.desc.x_staging != 1;
+  const bool use_fb = fbi >= 0 && p.desc.x_staging != 1 &&
+                      (fp32 ? (k->fn_c32_fb != nullptr && k->fn_c32_res_fb != nullptr) : k->fn_c_fb != nullptr);
   const int L = use_fb ? p.segs[fbi].L : p.segs[so].L;
   // unit-stride tiles: 2 lines of a full-block plan (measured fastest; more
   // workgroups of fewer waves each), else 256 threads, which amortise the
@@ -634,7 +635,9 @@ cb_status launch_wg(const Plan &p, const Geo &g, const double *in, double *out, 
   // phase C adding its correction to x
   for (int it = 0; it <= iters && e == hipSuccess; ++it) {
     const void *fa = it == 0 ? k->fn_a : k->fn_a_res;
-    const void *fc = !fp32 ? (use_fb ? k->fn_c_fb : k->fn_c) : (it == 0 ? k->fn_c32 : k->fn_c32_res);
+    const void *fc = !fp32     ? (use_fb ? k->fn_c_fb : k->fn_c)
+                     : it == 0 ? (use_fb ? k->fn_c32_fb : k->fn_c32)
+                               : (use_fb ? k->fn_c32_res_fb : k->fn_c32_res);
     e = hipLaunchKernel(fa, grid_a, dim3(kNTA), args, lds_a, stream);
     if (e == hipSuccess)
       e = hipLaunchKernel(k->fn_b, dim3((unsigned)((g.nlines + WB - 1) / WB)), dim3(NTB), args, lds_b, stream);

@@ -105,6 +105,7 @@ struct WgKernel {
   // with an FP32 interior solve storing x, and adding its correction to x
   const void *fn_a_res, *fn_c32, *fn_c32_res;
   const void *fn_c_fb;             // FP64 phase C on whole partitions (full-block plans)
+  const void *fn_c32_fb, *fn_c32_res_fb;  // ... and its FP32 + refinement forms
 };
 
 // Persistent batched launch: queue header and one work-table entry per item.

@@ -284,8 +284,15 @@ __device__ __forceinline__ void wg_solve_interior(const WgArgs &a, const LanePos
         if (k >= m - R && k < m) v[k] -= select_idx(tail, k - (m - R));
     }
   }
-  if constexpr (FB) {
+  if constexpr (FB && sizeof(T) == sizeof(double)) {
     solve_segment<R, M, T, true, CSRC_GLOBAL, ILU, true, TP>(v, sg, p, type, M, xc, nullptr, &pre);
+  } else if constexpr (FB) {  // the FP32 interior solve of the refinement pattern
+    T vt[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) vt[k] = (T)v[k];
+    solve_segment<R, M, T, true, CSRC_GLOBAL, ILU, true, TP>(vt, sg, p, type, M, xc, nullptr, &pre);
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (double)vt[k];
   } else if constexpr (sizeof(T) == sizeof(double)) {
     if (a.coef_lds)
       solve_segment<R, M, double, false, CSRC_LDS, ILU>(v, sg, p, type, m, xc, coef_lds);

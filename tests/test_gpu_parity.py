@@ -313,6 +313,31 @@ def test_long_fp32_lines_default_partitions(gpu, axis):
     assert relerr(x, oracle.solve_axis(b.numpy(), axis, TRI)) <= 1e-12
 
 
+@pytest.mark.parametrize("rows", [256, 512, 1024])
+@pytest.mark.parametrize("P", [4, 16])
+def test_full_block_fp32_refinement(gpu, rows, P):
+    """FP32 (+ FP64 refinement) on unit-stride tridiagonal lines of equal
+    partitions: phase C solves each whole partition as one block in FP32,
+    and each refinement iteration adds its correction to x in place (the
+    interface rows included).  Solve (cyclic and acyclic) and fused
+    derivative to 1e-12; plain FP32 to its bound."""
+    n = rows * P
+    shape = shape_with(0, n, (5, 3))
+    b = synth.random_uniform(shape, seed=rows + P)
+    for cyclic in (True, False):
+        plan = cb.Plan(TRI, n, partitions=P, precision="fp32_refine", cyclic=cyclic)
+        assert plan.info()["fullblock_seg"] >= 0
+        x = cb.solve(plan, b.to(gpu), 0).cpu().numpy()
+        assert relerr(x, oracle.solve_axis(b.numpy(), 0, TRI, cyclic=cyclic)) <= 1e-12, cyclic
+    f, _ = synth.random_modes(shape, seed=rows)
+    lo, c = deriv_stencil(schemes.DERIV6, n)
+    ref = oracle.apply_axis(f.numpy(), 0, TRI, lo, c)
+    for prec, tol in (("fp32_refine", 1e-12), ("fp32", fp32_bound(TRI))):
+        plan = cb.Plan(TRI, n, partitions=P, precision=prec)
+        out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), 0).cpu().numpy()
+        assert relerr(out, ref) <= tol, prec
+
+
 @pytest.mark.parametrize("P", [4, 16])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("bands", ["tri", "penta", "hept"])
