@@ -173,12 +173,19 @@ def poisson_requests(count, rate_hz, seed=0, side_lo=32, side_hi=1024, max_point
 
 
 class GpuExecutor:
-    """Runs request groups as one batched launch per stream slot."""
+    """Runs request groups as one batched launch per stream slot.
+
+    `precision` defaults to FP64: each line is read and written once either
+    way, and FP32 with FP64 refinement runs the reduction at least twice per
+    line with both precisions' state in registers, which costs more than
+    FP64 arithmetic saves (measured at saturation on the served request
+    mix: 162-165 GDOF/s FP64, 91-92 FP32 + refinement); "fp32_refine"
+    remains available."""
 
     # share of the device's free memory that admission may hand to requests
     BUDGET_FRACTION = 0.8
 
-    def __init__(self, slots=8, precision="fp32_refine", refine_iters=0, rows_per_lane=0, device="cuda:0",
+    def __init__(self, slots=8, precision="fp64", refine_iters=0, rows_per_lane=0, device="cuda:0",
                  on_result=None):
         import torch
         from . import cb
