@@ -285,7 +285,26 @@ __global__ __launch_bounds__((line_max_threads<R, M, T, MODE, UNI>())) void k_li
     const uint32_t j = tile % X, s = tile / X;
     tile = j * q + (j < rem ? j : rem) + s;
   }
-  line_tile<R, M, T, MODE, Q, UNI, ILU, COPY>(a, (int64_t)tile, smem);
+  if constexpr (sizeof(T) == 4 && UNI && M >= 8 && (M >= 12 || R >= 2)) {
+    // FP32 uniform lanes of 12 or more rows (8 or more for r >= 2): the
+    // arguments are read from the kernel argument segment (where `a`, the
+    // only explicit argument, sits at offset 0) through a pointer the
+    // compiler cannot trace back to it, so each field is loaded (a scalar
+    // load) where it is used instead of all being loaded at entry and held
+    // in SGPRs for the whole kernel, which next to the FP32 reduction and the
+    // FP64 refinement state spills SGPRs into VGPR lanes (16-row lanes:
+    // 194-256 VGPRs and 2 waves per SIMD, against 121-134 and 3-4 this way).
+    // Where nothing spills (8-row tridiagonal lanes, general layouts) the
+    // loads at the point of use only add latency, so those keep the plain
+    // form.  (Taking the address of `a` instead would make the compiler copy
+    // it to private memory.)
+    using ArgsC = __attribute__((address_space(4))) const LineArgs;
+    ArgsC *ap = (ArgsC *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(ap));
+    line_tile<R, M, T, MODE, Q, UNI, ILU, COPY>(*(const LineArgs *)ap, (int64_t)tile, smem);
+  } else {
+    line_tile<R, M, T, MODE, Q, UNI, ILU, COPY>(a, (int64_t)tile, smem);
+  }
 }
 
 
