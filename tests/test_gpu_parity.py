@@ -464,6 +464,31 @@ def test_fp32_and_refinement(gpu, bands, axis):
     assert e32 <= fp32_bound(bd)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bands", ["tri", "penta"])
+@pytest.mark.parametrize("n,rpl", [(384, 12), (384, 0), (512, 16), (512, 8), (512, 0)])
+def test_fp32_uniform_lanes(gpu, axis, bands, n, rpl):
+    """Plain FP32 and FP32 + refinement (automatic count) on uniform lanes of
+    8-16 rows, unit-stride and strided: the instances that read their
+    kernel arguments at the point of use (12-16 rows, 8 with r = 2) and the
+    ones that load them at entry, fused derivative against the oracle."""
+    bd = TRI if bands == "tri" else PENTA
+    f, _ = synth.random_modes(shape_with(axis, n, (6, 40)), seed=3 * n + axis)
+    lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
+    ref = oracle.apply_axis(f.numpy(), axis, bd, lo, c)
+    st = cb.Stencil(lo, c)
+    fd = f.to(gpu)
+    for prec, tol in (("fp32_refine", 1e-12), ("fp32", fp32_bound(bd))):
+        plan = cb.Plan(bd, n, precision=prec, rows_per_lane=rpl)
+        info = plan.info()
+        assert info["uniform"] == 1
+        if rpl:
+            assert info["rows_per_lane" if axis == 0 else "rows_per_lane_strided"] == rpl
+        out = cb.apply_derivative(plan, st, fd, axis).cpu().numpy()
+        plan.close()
+        assert relerr(out, ref) <= tol, (prec, relerr(out, ref))
+
+
 def fp32_bound(bands):
     """Error bound of a plain FP32 solve: 1e-6, the target, when the matrix
     allows it; else 2 kappa u, kappa the ratio of the extreme values of the
