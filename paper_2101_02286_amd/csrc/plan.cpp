@@ -997,8 +997,22 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
       // (FP32: up to 12 rows per lane, measured faster than 6 at n = 384)
       // (32-row lanes always eliminate: not when generalized PCR is asked for)
       const int m_max_s = d.precision == CB_FP64 ? (d.interior == 1 ? 16 : 32) : std::max(m_max, 12);
-      s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max_s,
-                        d.interior ? d.interior : 3, lcap);
+      // FP32 lines whose rows split into uniform lanes of 16 take those for
+      // r >= 2 from n = 256 and for r = 1 at n = 512..1024 (at 512^3 y / z
+      // with one refinement: 214 / 157 -> 242 / 223 GDOF/s tridiagonal,
+      // 144 / 99 -> 150 / 138 pentadiagonal); tridiagonal lines of 256 or of
+      // 2048 and more rows, and general layouts, run faster on 8
+      const bool fp32_16 = d.precision != CB_FP64 && n >= 256 && (R >= 2 || (n >= 512 && n <= 1024));
+      s = CB_ERR_UNSUPPORTED;
+      if (fp32_16) {
+        std::string m16;
+        s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, m16, 0, PREF_S, 16, d.interior ? d.interior : 3,
+                          lcap);
+        if (s == CB_OK && !(alt.uniform && alt.M == 16)) s = CB_ERR_UNSUPPORTED;
+      }
+      if (s != CB_OK)
+        s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max_s,
+                          d.interior ? d.interior : 3, lcap);
       if (s != CB_OK && d.interior == 0)
         s = build_segment(n, R, cyclic, per_row, line_coef, 0, alt, msg, 0, PREF_S, m_max, 1, lcap);
       if (s != CB_OK) return s;
