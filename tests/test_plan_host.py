@@ -314,6 +314,25 @@ def test_strided_layout_reproduces_oracle(name, n):
     assert p.array(11, 1 if two else 0)[6] == info["interior_elimination_strided"]
 
 
+@pytest.mark.parametrize("name,n,rows", [("tri", 256, 8), ("tri", 512, 16), ("tri", 1024, 16), ("tri", 2048, 8),
+                                         ("tri", 384, 12), ("tri", 500, 8), ("penta", 128, 8), ("penta", 256, 16),
+                                         ("penta", 2048, 16), ("penta", 500, 8)])
+def test_fp32_strided_rows_per_lane(name, n, rows):
+    """FP32 plans lay strided lines out on uniform 16-row lanes where those
+    measured fastest (r >= 2 from n = 256, r = 1 at n = 512..1024), else as
+    before: 12 rows at n = 384, 8 rows for the other tridiagonal lengths and
+    for general layouts (ragged n); and the layout still solves the system."""
+    bands = _bands(name)
+    p = cb.Plan(bands, n, precision="fp32_refine", host_only=True)
+    info = p.info()
+    assert info["rows_per_lane_strided"] == rows
+    seg = 1 if (info["lanes_strided"] != info["lanes"] or
+                info["interior_elimination_strided"] != info["interior_elimination"]) else 0
+    b = np.random.default_rng(n).standard_normal((2, n))
+    ref = oracle.solve_lines(b, bands)
+    assert np.abs(plan_emulator.solve(p, b, seg) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("name", ["tri", "penta"])
 @pytest.mark.parametrize("n,rpl", [(512, 8), (512, 16), (384, 12), (613, 16), (200, 8), (512, 32), (64, 32),
                                    (32, 32)])
