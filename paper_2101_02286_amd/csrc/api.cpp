@@ -365,10 +365,12 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
   if (p.desc.lines_per_wg > 0) {
     W = p.desc.lines_per_wg;
   } else if (mode == MODE_X) {
-    // staged unit-stride lines: one line per workgroup measured best (512^3),
-    // but at least one wavefront per workgroup for short lines; direct loads:
+    // staged unit-stride lines: one line per workgroup measured best for
+    // uniform lanes (512^3), but at least one wavefront per workgroup for
+    // short lines; general FP64 layouts (ragged n) 256 threads (n = 200-1000:
+    // 3-17 % faster than one 64-thread wavefront or line); direct loads:
     // 512-thread workgroups
-    W = stage_x ? std::max(1, 64 / L) : std::max(1, 512 / L);
+    W = stage_x ? std::max(1, (uni || fp32 ? 64 : 256) / L) : std::max(1, 512 / L);
   } else {
     // adjacent lines: 16 (128-byte row segments), 32 with 32 rows per lane.
     // FP32 lines with refinement: at most 512 threads unless that leaves
