@@ -379,6 +379,13 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
     // 8 vs 16 lines of 64 lanes)
     W = std::max(1, std::min(sp.M == 32 ? 32 : 16, 1024 / L));
     if (fp32 && p.refine_iters > 0) W = std::min(W, std::max(8, 512 / L));
+    // FP64 general layouts of r >= 2 over 64 lanes (ragged n of 513..1024
+    // rows), on lines that do not form one contiguous run across planes
+    // (e.g. along y of a C-order array): 8 lines, 512 threads (pentadiagonal
+    // n = 613-1000 along y: 5-18 % faster than 16 lines; along z the two
+    // measured either way by plane size)
+    const bool contiguous = g.su == 1 && (g.nlines <= g.nu || g.sv == g.nu);
+    if (!fp32 && !uni && p.R >= 2 && L == 64 && !contiguous) W = 8;
   }
   // LDS: two exchange regions of max(2Q, 2r) doubles per thread (2r when the
   // unit-stride tile is staged: its halo comes from the tile), within the
@@ -921,6 +928,10 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       // 512 threads, or 16 lines (8 with FP32 refinement, as in launch_line)
       // where lanes need more
       if (bk) nt = std::min(bk->threads, std::max(512, (fp && p.refine_iters > 0 ? 8 : 16) * L));
+      // 8 lines of 64 lanes for FP64 general layouts of r >= 2 on lines
+      // that are not one contiguous run across planes (as in launch_line)
+      const bool contiguous = g.su == 1 && (g.nlines <= g.nu || g.sv == g.nu);
+      if (bk && !fp && !uni && p.R >= 2 && L == 64 && !contiguous) nt = std::min(nt, 512);
       if (bk && L <= nt) W = nt / L;
     }
     if (!bk || W == 0)
