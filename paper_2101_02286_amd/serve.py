@@ -179,7 +179,7 @@ class GpuExecutor:
     way, and FP32 with FP64 refinement runs the reduction at least twice per
     line with both precisions' state in registers, which costs more than
     FP64 arithmetic saves (measured at saturation on the served request
-    mix: 162-165 GDOF/s FP64, 91-92 FP32 + refinement); "fp32_refine"
+    mix: 170-173 GDOF/s FP64, 89-93 FP32 + refinement); "fp32_refine"
     remains available."""
 
     # share of the device's free memory that admission may hand to requests
