@@ -1024,9 +1024,14 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     p.M = p.segs[0].M;
     p.L = p.segs[0].L;
     p.wg_start = {0, n};
-    if (d.precision == CB_FP64 && n > 4096 && !d.rows_per_lane && !d.lines_per_wg) {
+    // ragged FP64 lines of 1025..4096 rows (general strided layouts of
+    // 128-256 lanes): strided launches run ~512-row workgroup partitions
+    // instead (n = 1030-4000 along y / z: 84-174 -> 122-233 GDOF/s; the
+    // uniform layouts of 2048 and 4096 rows are faster whole)
+    const bool ragged_mid = n > 1024 && n <= 4096 && !p.segs[p.seg_s].uniform;
+    if (d.precision == CB_FP64 && (n > 4096 || ragged_mid) && !d.rows_per_lane && !d.lines_per_wg) {
       cb_plan_desc dw = d;
-      dw.partitions = (n + 512) / 1024;
+      dw.partitions = n > 4096 ? (n + 512) / 1024 : (n + 511) / 512;
       dw.x_staging = 0;
       dw.interior = 0;
       auto w = std::make_shared<Plan>();

@@ -301,6 +301,31 @@ def test_partitioned_fp32_refinement(gpu, P, axis, bands):
     assert relerr(out32, ref) <= fp32_bound(bd)
 
 
+@pytest.mark.parametrize("axis", [1, 2, 0])
+@pytest.mark.parametrize("n,bands,cyclic", [(1100, "tri", True), (3000, "penta", True), (2500, "tri", True),
+                                            (2048, "penta", False)])
+def test_ragged_mid_length_strided_partitions(gpu, axis, n, bands, cyclic):
+    """FP64 lines of 1025..4096 rows on general lane layouts: strided launches
+    run in ~512-row workgroup partitions (unit-stride lines stay whole); the
+    fused derivative (solve only for the acyclic case) against the oracle."""
+    bd = TRI if bands == "tri" else PENTA
+    plan = cb.Plan(bd, n, cyclic=cyclic)
+    assert plan.info()["partitions_strided"] == (n + 511) // 512
+    assert plan.info()["partitions"] == 1
+    shape = shape_with(axis, n, (5, 7))
+    if cyclic:
+        f, _ = synth.random_modes(shape, seed=n + axis)
+        lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
+        out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+        ref = oracle.apply_axis(f.numpy(), axis, bd, lo, c)
+    else:
+        b = synth.random_uniform(shape, seed=n + axis)
+        out = cb.solve(plan, b.to(gpu), axis).cpu().numpy()
+        ref = oracle.solve_axis(b.numpy(), axis, bd, cyclic=False)
+    plan.close()
+    assert relerr(out, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("axis", [0, 2])
 def test_long_fp32_lines_default_partitions(gpu, axis):
     """FP32 + refinement lines longer than one workgroup (n > 8192) are split

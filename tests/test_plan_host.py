@@ -388,9 +388,18 @@ def test_thirty_two_rows_need_uniform_elimination():
 
 def test_long_lines_split_strided_launches():
     """FP64 one-partition plans with n > 4096 solve strided lines in ~1024-row
-    workgroup partitions (unit-stride lines stay whole)."""
+    workgroup partitions, ragged ones of 1025..4096 rows (general layouts) in
+    ~512-row partitions (unit-stride lines stay whole)."""
     tri = [1 / 3, 1.0, 1 / 3]
     assert cb.Plan(tri, 4096, host_only=True).info()["partitions_strided"] == 1
+    assert cb.Plan(tri, 2048, host_only=True).info()["partitions_strided"] == 1
+    assert cb.Plan(tri, 1024, host_only=True).info()["partitions_strided"] == 1
+    assert cb.Plan(tri, 1000, host_only=True).info()["partitions_strided"] == 1
+    for n, P in ((1025, 3), (1100, 3), (2000, 4), (4000, 8)):
+        i = cb.Plan(tri, n, host_only=True).info()
+        assert (i["partitions"], i["partitions_strided"]) == (1, P)
+    assert cb.Plan(tri, 2048, cyclic=False, host_only=True).info()["partitions_strided"] == 4
+    assert cb.Plan(tri, 2500, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
     i = cb.Plan(tri, 8192, host_only=True).info()
     assert (i["partitions"], i["partitions_strided"]) == (1, 8)
     assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
