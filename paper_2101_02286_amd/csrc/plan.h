@@ -148,9 +148,10 @@ struct Plan {
   const double *d_mats = nullptr;
   const double *d_bfun = nullptr;
   const double *d_bands = nullptr;     // n*(2r+1) per-row bands
-  // long FP64 lines (n > 4096) of a one-partition plan: strided launches run
-  // the same matrix split into workgroup partitions of about 1024 rows, since
-  // a whole line per workgroup would leave room for only a few adjacent lines
+  // long FP64 lines (n > 4096) of a one-partition plan, and ragged ones of
+  // 1025..4096 rows on general lane layouts: strided launches run the same
+  // matrix split into workgroup partitions of about 512 rows, since a whole
+  // line per workgroup would leave room for only a few adjacent lines
   std::shared_ptr<Plan> strided_wg;
   std::shared_ptr<ScratchCache> sc = std::make_shared<ScratchCache>();
 };

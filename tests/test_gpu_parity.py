@@ -732,11 +732,11 @@ def test_longest_one_partition_lines(gpu, axis):
 @pytest.mark.parametrize("axis", [1, 2])
 @pytest.mark.parametrize("bands", ["tri", "penta"])
 def test_long_strided_lines_use_partitions(gpu, axis, bands):
-    """n = 8192 strided lines run as 8 workgroup partitions (solve and fused derivative)."""
+    """n = 8192 strided lines run as 16 workgroup partitions (solve and fused derivative)."""
     bd = TRI if bands == "tri" else PENTA
     n = 8192
     plan = cb.Plan(bd, n)
-    assert plan.info()["partitions_strided"] == 8
+    assert plan.info()["partitions_strided"] == 16
     shape = shape_with(axis, n, (5, 3))
     b = synth.random_uniform(shape, seed=axis)
     x = cb.solve(plan, b.to(gpu), axis).cpu().numpy()

@@ -387,9 +387,9 @@ def test_thirty_two_rows_need_uniform_elimination():
 
 
 def test_long_lines_split_strided_launches():
-    """FP64 one-partition plans with n > 4096 solve strided lines in ~1024-row
-    workgroup partitions, ragged ones of 1025..4096 rows (general layouts) in
-    ~512-row partitions (unit-stride lines stay whole)."""
+    """FP64 one-partition plans with n > 4096, and ragged ones of 1025..4096
+    rows (general layouts), solve strided lines in ~512-row workgroup
+    partitions (unit-stride lines stay whole)."""
     tri = [1 / 3, 1.0, 1 / 3]
     assert cb.Plan(tri, 4096, host_only=True).info()["partitions_strided"] == 1
     assert cb.Plan(tri, 2048, host_only=True).info()["partitions_strided"] == 1
@@ -401,7 +401,10 @@ def test_long_lines_split_strided_launches():
     assert cb.Plan(tri, 2048, cyclic=False, host_only=True).info()["partitions_strided"] == 4
     assert cb.Plan(tri, 2500, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
     i = cb.Plan(tri, 8192, host_only=True).info()
-    assert (i["partitions"], i["partitions_strided"]) == (1, 8)
+    assert (i["partitions"], i["partitions_strided"]) == (1, 16)
+    # lines longer than one workgroup holds are partitioned plans already
+    i = cb.Plan(tri, 32768, host_only=True).info()
+    assert (i["partitions"], i["partitions_strided"]) == (32, 32)
     assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
     assert cb.Plan(tri, 8192, rows_per_lane=16, host_only=True).info()["partitions_strided"] == 1
 
