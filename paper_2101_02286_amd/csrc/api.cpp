@@ -35,6 +35,7 @@ struct BatchLaunch {
 // as its own phase launches, with its partition scratch in the workspace.
 struct WgItem {
   cb_plan_t plan;
+  const Plan *wp;  // what runs: the plan (P > 1) or its partitioned strided copy
   cb_grid grid;
   int axis;
   const double *in;
@@ -282,16 +283,27 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Workspace bytes of a batch: queue headers and work table, then from a
 // 256-byte boundary the partition scratch of each P > 1 item.
+// The plan a batch item runs as workgroup-partition phase launches, as a
+// single call of it would: the plan itself when it has P > 1, its
+// partitioned copy for strided lines when it has one; else nullptr (the
+// item's lines run whole in the batched line kernels).
+const Plan *batch_wg_plan(const Plan &p, const Geo &g) {
+  if (p.P != 1) return &p;
+  if (g.rs != 1 && p.strided_wg) return p.strided_wg.get();
+  return nullptr;
+}
+
 size_t batch_bytes(const cb_batch_item *items, int32_t n_items) {
   const size_t nn = (size_t)(n_items > 0 ? n_items : 0);
   const size_t table = batch_items_offset(nn) + nn * sizeof(BatchItemDev);
   size_t scratch = 0;
   for (int32_t i = 0; i < n_items; ++i) {
     const cb_batch_item &it = items[i];
-    if (!it.plan || it.plan->p.P == 1) continue;
+    if (!it.plan) continue;
     Geo g;
     if (geometry(&it.grid, it.axis, g) != CB_OK) continue;
-    scratch += align256(wg_scratch_bytes(it.plan->p, g.nlines));
+    const Plan *wp = batch_wg_plan(it.plan->p, g);
+    if (wp) scratch += align256(wg_scratch_bytes(*wp, g.nlines));
   }
   return scratch ? align256(table) + scratch : table;
 }
@@ -860,16 +872,17 @@ cb_status cb_batch_build(const cb_batch_item *items, int32_t n_items, void *work
       if (!p.desc.cyclic) return fail(CB_ERR_INVALID_ARG, "cb_batch_build: a stencil needs a cyclic plan");
     }
     if (g.nlines >= (int64_t(1) << 31)) return fail(CB_ERR_UNSUPPORTED, "cb_batch_build: more than 2^31 lines");
-    if (p.P != 1) {  // its own phase launches, scratch in the workspace
+    if (const Plan *wp = batch_wg_plan(p, g)) {  // its own phase launches, scratch in the workspace
       WgItem w;
       w.plan = it.plan;
+      w.wp = wp;
       w.grid = it.grid;
       w.axis = it.axis;
       w.in = it.in;
       w.out = it.out;
       w.has_stencil = it.stencil != nullptr;
       if (it.stencil) w.stencil = *it.stencil;
-      w.sc_bytes = wg_scratch_bytes(p, g.nlines);
+      w.sc_bytes = wg_scratch_bytes(*wp, g.nlines);
       w.sc_off = sc_next;
       sc_next += align256(w.sc_bytes);
       wg_items.push_back(w);
@@ -1124,8 +1137,7 @@ cb_status cb_batch_launch(void *workspace, int32_t max_ctas, void *stream) {
     if (s) return s;
     if (g.nlines == 0) continue;
     const FixedScratch fs{static_cast<char *>(workspace) + w.sc_off, w.sc_bytes};
-    s = launch_wg(w.plan->p, g, w.in, w.out, w.has_stencil ? &w.stencil : nullptr, static_cast<hipStream_t>(stream),
-                  &fs);
+    s = launch_wg(*w.wp, g, w.in, w.out, w.has_stencil ? &w.stencil : nullptr, static_cast<hipStream_t>(stream), &fs);
     if (s) return s;
   }
   return CB_OK;

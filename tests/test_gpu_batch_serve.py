@@ -149,12 +149,15 @@ def test_mixed_plans_one_batch(gpu):
 
 def _partitioned_batch_items(gpu):
     """Items split over workgroup partitions (FP64 and FP32 + refinement,
-    fused and plain, cyclic and acyclic, r = 1..3) beside one-partition ones."""
+    fused and plain, cyclic and acyclic, r = 1..3) beside one-partition ones,
+    and one-partition plans whose strided launches run a partitioned copy
+    (P = 0 below: a ragged 1100-row line and an 8192-row one)."""
     HEPT = schemes.bands_collocated(schemes.DERIV12H)
     cases = [  # (bands, scheme, n, P, precision, axis, fused, cyclic)
         (TRI, "tri6", 4096, 4, "fp64", 0, True, True), (PENTA, "penta10", 3003, 3, "fp32_refine", 2, True, True),
         (TRI, "tri6", 2000, 5, "fp64", 1, False, False), (HEPT, "hept12", 2048, 4, "fp32_refine", 0, False, True),
         (TRI, "tri6", 256, 1, "fp64", 1, True, True), (PENTA, "penta10", 300, 1, "fp32_refine", 0, False, True),
+        (TRI, "tri6", 1100, 0, "fp64", 1, True, True), (PENTA, "penta10", 8192, 0, "fp64", 2, False, True),
     ]
     items, singles, refs = [], [], []
     for k, (bands, scheme, n, P, prec, axis, fused, cyclic) in enumerate(cases):
@@ -162,7 +165,9 @@ def _partitioned_batch_items(gpu):
         shape.insert(axis, n)
         shape = (shape[2], shape[1], shape[0])
         plan = cb.Plan(bands, n, partitions=P, precision=prec, cyclic=cyclic)
-        assert plan.info()["partitions"] == P
+        assert plan.info()["partitions"] == max(P, 1)
+        if P == 0:
+            assert plan.info()["partitions_strided"] > 1 and axis > 0
         if fused:
             f, _ = synth.random_modes(shape, seed=k)
             lo, c = stencil_for(scheme, n)
