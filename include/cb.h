@@ -283,10 +283,12 @@ typedef struct {
   int32_t interior_elimination;  /* 1 when lane interiors use banded elimination */
   int32_t interior_elimination_strided; /* the same for strided launches */
   int32_t partitions_strided;    /* workgroup partitions of strided launches
-                                    (FP64 one-partition plans with n > 4096,
-                                    or ragged n > 1024 on a general lane
-                                    layout, split strided lines into
-                                    ~512-row parts) */
+                                    (one-partition plans with n > 4096,
+                                    or on a general lane layout with
+                                    n > 1024 in FP64, n > 2048 in FP32,
+                                    split strided lines into ~512-row
+                                    parts; in-place FP32 + refinement
+                                    solves keep whole lines) */
   int32_t boundary_window;       /* P > 1: rows at each end of an interior
                                     block that phase A reads (the kept part
                                     of the boundary rows of D_i^{-1}) */

@@ -342,8 +342,9 @@ void residual_bands(const Plan &p, LineArgs &a) {
 // copy: the same launch with the copy-only kernel (no stencil, no solve).
 cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out, const cb_stencil *st,
                       hipStream_t stream, const FixedScratch *fs, bool copy = false) {
-  // long strided lines: workgroup partitions of the same matrix
-  if (g.rs != 1 && p.strided_wg) {
+  // long strided lines: workgroup partitions of the same matrix (whole lines
+  // for in-place FP32 + refinement, whose partitioned form re-reads b)
+  if (g.rs != 1 && p.strided_wg && !(in == out && p.strided_wg->refine_iters > 0)) {
     if (copy) return fail(CB_ERR_UNSUPPORTED, "cb_copy_lines: this launch runs in workgroup partitions");
     return launch_wg(*p.strided_wg, g, in, out, st, stream, fs);
   }

@@ -1027,9 +1027,13 @@ cb_status build_plan(const cb_plan_desc &d, Plan &p, std::string &msg) {
     // ragged FP64 lines of 1025..4096 rows (general strided layouts of
     // 128-256 lanes): strided launches run ~512-row workgroup partitions
     // instead (n = 1030-4000 along y / z: 84-174 -> 122-233 GDOF/s; the
-    // uniform layouts of 2048 and 4096 rows are faster whole)
-    const bool ragged_mid = n > 1024 && n <= 4096 && !p.segs[p.seg_s].uniform;
-    if (d.precision == CB_FP64 && (n > 4096 || ragged_mid) && !d.rows_per_lane && !d.lines_per_wg) {
+    // uniform layouts of 2048 and 4096 rows are faster whole).  FP32 lines
+    // the same from 4097 rows and, on general layouts, from 2049 (FP32 +
+    // refinement n = 2500-8192 along y / z: 12-65 -> 41-101 GDOF/s; at
+    // 1100 rows whole lines are as fast)
+    const bool general_s = !p.segs[p.seg_s].uniform;
+    const bool split = n > 4096 || (general_s && n > (d.precision == CB_FP64 ? 1024 : 2048));
+    if (split && !d.rows_per_lane && !d.lines_per_wg) {
       cb_plan_desc dw = d;
       // (~512-row partitions also beyond 4096 rows, up to the 16384 rows of a
       // one-partition plan: n = 5000-16384 tridiagonal y / z 5-13 % faster

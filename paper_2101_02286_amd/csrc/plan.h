@@ -148,8 +148,8 @@ struct Plan {
   const double *d_mats = nullptr;
   const double *d_bfun = nullptr;
   const double *d_bands = nullptr;     // n*(2r+1) per-row bands
-  // long FP64 lines (n > 4096) of a one-partition plan, and ragged ones of
-  // 1025..4096 rows on general lane layouts: strided launches run the same
+  // long lines (n > 4096) of a one-partition plan, and ragged ones on
+  // general lane layouts (FP64 n > 1024, FP32 n > 2048): strided launches run the same
   // matrix split into workgroup partitions of about 512 rows, since a whole
   // line per workgroup would leave room for only a few adjacent lines
   std::shared_ptr<Plan> strided_wg;

@@ -326,6 +326,31 @@ def test_ragged_mid_length_strided_partitions(gpu, axis, n, bands, cyclic):
     assert relerr(out, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("n,bands", [(2500, "tri"), (8192, "penta"), (3000, "tri")])
+def test_fp32_strided_partition_copies(gpu, axis, n, bands):
+    """FP32 + refinement one-partition plans whose strided launches run a
+    ~512-row partitioned copy (n > 4096, or general layouts above 2048 rows):
+    fused derivative and out-of-place solve to 1e-12, and an in-place solve
+    (which runs whole lines, as the partitioned refinement re-reads b)."""
+    bd = TRI if bands == "tri" else PENTA
+    plan = cb.Plan(bd, n, precision="fp32_refine")
+    assert plan.info()["partitions"] == 1
+    assert plan.info()["partitions_strided"] == (n + 511) // 512
+    shape = shape_with(axis, n, (5, 6))
+    f, _ = synth.random_modes(shape, seed=n + axis)
+    lo, c = deriv_stencil(schemes.DERIV6 if bands == "tri" else schemes.DERIV10, n)
+    out = cb.apply_derivative(plan, cb.Stencil(lo, c), f.to(gpu), axis).cpu().numpy()
+    assert relerr(out, oracle.apply_axis(f.numpy(), axis, bd, lo, c)) <= 1e-12
+    b = synth.random_uniform(shape, seed=n + axis + 1)
+    ref = oracle.solve_axis(b.numpy(), axis, bd)
+    assert relerr(cb.solve(plan, b.to(gpu), axis).cpu().numpy(), ref) <= 1e-12
+    bi = b.to(gpu)
+    cb.solve(plan, bi, axis, out=bi)
+    assert relerr(bi.cpu().numpy(), ref) <= 1e-12
+    plan.close()
+
+
 @pytest.mark.parametrize("axis", [0, 2])
 def test_long_fp32_lines_default_partitions(gpu, axis):
     """FP32 + refinement lines longer than one workgroup (n > 8192) are split

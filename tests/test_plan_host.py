@@ -387,9 +387,9 @@ def test_thirty_two_rows_need_uniform_elimination():
 
 
 def test_long_lines_split_strided_launches():
-    """FP64 one-partition plans with n > 4096, and ragged ones of 1025..4096
-    rows (general layouts), solve strided lines in ~512-row workgroup
-    partitions (unit-stride lines stay whole)."""
+    """One-partition plans with n > 4096, and ragged ones (general layouts) of
+    1025..4096 rows in FP64 or 2049..4096 in FP32, solve strided lines in
+    ~512-row workgroup partitions (unit-stride lines stay whole)."""
     tri = [1 / 3, 1.0, 1 / 3]
     assert cb.Plan(tri, 4096, host_only=True).info()["partitions_strided"] == 1
     assert cb.Plan(tri, 2048, host_only=True).info()["partitions_strided"] == 1
@@ -399,13 +399,15 @@ def test_long_lines_split_strided_launches():
         i = cb.Plan(tri, n, host_only=True).info()
         assert (i["partitions"], i["partitions_strided"]) == (1, P)
     assert cb.Plan(tri, 2048, cyclic=False, host_only=True).info()["partitions_strided"] == 4
-    assert cb.Plan(tri, 2500, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
+    # FP32: from 4097 rows, and from 2049 on general layouts
+    for n, P in ((1100, 1), (2048, 1), (2500, 5), (4096, 1), (5000, 10)):
+        assert cb.Plan(tri, n, precision="fp32_refine", host_only=True).info()["partitions_strided"] == P
     i = cb.Plan(tri, 8192, host_only=True).info()
     assert (i["partitions"], i["partitions_strided"]) == (1, 16)
     # lines longer than one workgroup holds are partitioned plans already
     i = cb.Plan(tri, 32768, host_only=True).info()
     assert (i["partitions"], i["partitions_strided"]) == (32, 32)
-    assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 1
+    assert cb.Plan(tri, 8192, precision="fp32_refine", host_only=True).info()["partitions_strided"] == 16
     assert cb.Plan(tri, 8192, rows_per_lane=16, host_only=True).info()["partitions_strided"] == 1
 
 
