@@ -391,6 +391,9 @@ cb_status launch_line(const Plan &p, const Geo &g, const double *in, double *out
     // which cost more in larger workgroups: measured 189 vs 154 GDOF/s for
     // 8 vs 16 lines of 64 lanes)
     W = std::max(1, std::min(sp.M == 32 ? 32 : 16, 1024 / L));
+    // 128-row lines on 4 lanes of 32 rows: 64 lines (256 threads; 1-7 %
+    // faster than 32 along y and z)
+    if (sp.M == 32 && L == 4) W = 64;
     if (fp32 && p.refine_iters > 0) W = std::min(W, std::max(8, 512 / L));
     // FP64 general layouts of r >= 2 over 64 lanes (ragged n of 513..1024
     // rows), on lines that do not form one contiguous run across planes
